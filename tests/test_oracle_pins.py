@@ -1,0 +1,356 @@
+"""Pins of the FP64 oracle against what the mathematics fixes (CPU only).
+
+Each test checks one part of the oracle against an independent fact: a
+library routine, a theorem, a closed form, an independently constructed
+operator, or an invariant of the method. Paper: Dzanic & Martinelli,
+arXiv 2308.06196, Sec. 2 and Sec. 2.1.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+from scipy import optimize
+
+from oracle import oracle as orc
+from paper_2308_06196_amd import workloads as wl
+
+
+def P(**kw) -> orc.Problem:
+    base = dict(dim=1, order=2, nelem=(4,), xlo=(0.0,), xhi=(1.0,), nvel=(8, 4, 4),
+                vlo=(-4.0, -4.0, -4.0), vhi=(4.0, 4.0, 4.0), bc=((0, 0),), mu_ref=1e-2)
+    base.update(kw)
+    return orc.Problem(**base)
+
+
+def from_dict(pb) -> orc.Problem:
+    keys = ["dim", "order", "nelem", "xlo", "xhi", "nvel", "vlo", "vhi", "bc", "mu_ref",
+            "theta_ref", "omega", "gamma", "limiter", "newton_maxit", "newton_tol"]
+    return orc.Problem(**{k: pb[k] for k in keys})
+
+
+# --------------------------------------------------------------------------
+# 1-D operators (Sec. 2.1, spatial discretization)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", range(1, 8))
+def test_gauss_matches_library(n):
+    x, w = orc.gauss_legendre(n)
+    X, W = npleg.leggauss(n)
+    assert np.max(np.abs(x - X)) < 1e-15
+    assert np.max(np.abs(w - W)) < 2e-15
+
+
+@pytest.mark.parametrize("p", range(0, 7))
+def test_lagrange_exact_on_monomials(p):
+    xi, _ = orc.gauss_legendre(p + 1)
+    D, lL, lR = orc.lagrange_ops(xi)
+    for q in range(p + 1):
+        v = xi ** q
+        dv = q * xi ** (q - 1) if q else np.zeros_like(xi)
+        assert np.max(np.abs(D @ v - dv)) < 1e-12
+        assert abs(lR @ v - 1.0) < 1e-13
+        assert abs(lL @ v - (-1.0) ** q) < 1e-13
+    assert np.max(np.abs(D.sum(axis=1))) < 1e-12
+
+
+@pytest.mark.parametrize("p", range(0, 7))
+def test_dg_correction_identity(p):
+    """Theorem (FR recovers nodal DG at Gauss points): g_R'(xi_a) = l_a(1)/w_a and
+    g_L'(xi_a) = -l_a(-1)/w_a."""
+    xi, wq = orc.gauss_legendre(p + 1)
+    _, lL, lR = orc.lagrange_ops(xi)
+    GL, GR = orc.dg_correction(p, xi)
+    assert np.max(np.abs(GR - lR / wq)) < 1e-12 * max(1, np.max(np.abs(GR)))
+    assert np.max(np.abs(GL + lL / wq)) < 1e-12 * max(1, np.max(np.abs(GL)))
+
+
+# --------------------------------------------------------------------------
+# Velocity grid and trapezoid moments (Sec. 2.1, velocity discretization)
+# --------------------------------------------------------------------------
+
+def test_velocity_grid_layout():
+    pr = P(nvel=(4, 3, 2), vlo=(-1.0, -2.0, -3.0), vhi=(1.0, 2.0, 3.0))
+    u, w = orc.velocity_grid(pr)
+    assert u.shape == (24, 3)
+    # b_x fastest
+    assert np.allclose(u[:4, 0], [-1, -1 / 3, 1 / 3, 1]) and np.all(u[:4, 1] == -2.0)
+    assert np.allclose(u[4:8, 1], 0.0)
+    # 1-D trapezoid weights, tensor product; total = box volume
+    assert math.isclose(w.sum(), 2 * 4 * 6, rel_tol=1e-14)
+    assert math.isclose(w[0], (2 / 3 / 2) * (2 / 2) * (6 / 2), rel_tol=1e-14)
+
+
+@pytest.mark.parametrize("nv1,vmax,tol", [(16, 6.0, 2e-6), (24, 6.0, 1e-7), (40, 9.0, 1e-13)])
+def test_trapezoid_maxwellian_moments(nv1, vmax, tol):
+    """Moments of a sampled Maxwellian vs the closed form rho, rho U, rho|U|^2/2 + 3/2 rho theta.
+    The trapezoid rule is spectrally accurate; on [-6,6]^3 the truncated tails limit the
+    error to ~1e-8, on [-9,9]^3 with 40 nodes it reaches round-off."""
+    pr = P(nelem=(1,), order=0, nvel=(nv1,) * 3, vlo=(-vmax,) * 3, vhi=(vmax,) * 3)
+    prim = np.array([[1.3, 0.2, -0.1, 0.05, 0.9]])
+    f = orc.maxwellian(pr, prim)
+    Q = orc.moments(pr, f)[0]
+    rho, U, th = 1.3, np.array([0.2, -0.1, 0.05]), 0.9
+    exact = np.array([rho, *(rho * U), 0.5 * rho * U @ U + 1.5 * rho * th])
+    assert np.max(np.abs(Q - exact) / np.array([rho, rho, rho, rho, exact[4]])) < tol
+
+
+# --------------------------------------------------------------------------
+# Discretely conservative equilibrium (Sec. 2.1, DVM + Newton)
+# --------------------------------------------------------------------------
+
+def _dual_alpha(u, w, Q, a0):
+    """Independent solution of the DVM equilibrium: minimise the convex dual
+    sum_j w_j exp(alpha.psi_j) - alpha.Q with scipy (trust-region Newton)."""
+    psi = np.column_stack([np.ones(len(u)), u, 0.5 * (u * u).sum(1)])
+
+    def fun(a):
+        g = w * np.exp(psi @ a)
+        return g.sum() - a @ Q, psi.T @ g - Q
+
+    def hess(a):
+        g = w * np.exp(psi @ a)
+        return (psi * g[:, None]).T @ psi
+
+    r = optimize.minimize(fun, a0, jac=True, hess=hess, method="trust-exact",
+                          options={"gtol": 1e-15, "maxiter": 200})
+    return r.x
+
+
+def test_newton_fixed_point_on_sampled_maxwellian():
+    pr = P(nelem=(1,), order=0, nvel=(16,) * 3, vlo=(-6.0,) * 3, vhi=(6.0,) * 3)
+    f = orc.maxwellian(pr, np.array([[0.7, 0.3, 0.0, -0.2, 1.2]]))
+    Cc, d = orc.collision(pr, f)
+    # C = (g - f)/tau; sampled Maxwellians are exp(alpha.psi), so g == f. Newton starts
+    # from the continuous Maxwellian of the discrete moments (off by the quadrature
+    # error), needs one step, and then takes its polishing step: 3 residual evaluations.
+    Q = orc.moments(pr, f)[0]
+    rho, U = Q[0], Q[1:4] / Q[0]
+    Pp = (2.0 / 3.0) * (Q[4] - 0.5 * rho * U @ U)
+    g_minus_f = Cc * (pr.mu_ref / Pp)
+    assert np.linalg.norm(g_minus_f) / np.linalg.norm(f) < 1e-14
+    assert d["newton_fail"] == 0 and d["newton_it_max"] <= 3
+
+
+@pytest.mark.parametrize("nv1,maxit", [(8, 8), (16, 4), (24, 4)])
+def test_newton_conserves_and_matches_dual(nv1, maxit):
+    """sum_j w_j psi_j (g_j - f_j) = 0 to round-off for a random positive f, and the
+    root agrees with an independent convex-dual minimisation."""
+    pr = P(nelem=(1,), order=0, nvel=(nv1,) * 3, vlo=(-6.0,) * 3, vhi=(6.0,) * 3)
+    u, w = orc.velocity_grid(pr)
+    f = orc.maxwellian(pr, np.array([[1.1, 0.15, -0.1, 0.05, 1.0]]))
+    f = f * wl.perturbation(7, f.shape, 0.3)
+    Q = orc.moments(pr, f)[0]
+    st, alpha, its, res = orc.newton_node(pr, Q)
+    assert st == 0 and its <= maxit
+    psi = np.column_stack([np.ones(len(u)), u, 0.5 * (u * u).sum(1)])
+    g = np.exp(psi @ alpha)
+    cons = (w[:, None] * psi * (g - f[0, 0])[:, None]).sum(0)
+    scale = np.array([Q[0], Q[0], Q[0], Q[0], Q[4]])
+    assert np.max(np.abs(cons) / scale) < 1e-13
+    a_dual = _dual_alpha(u, w, Q, alpha * (1 + 1e-3))
+    g_dual = np.exp(psi @ a_dual)
+    assert np.linalg.norm(g - g_dual) / np.linalg.norm(g) < 1e-10
+
+
+def test_newton_rejects_unrealizable():
+    pr = P(nelem=(1,), order=0)
+    st, *_ = orc.newton_node(pr, np.array([-1.0, 0, 0, 0, 1.0]))
+    assert st == 2
+    st, *_ = orc.newton_node(pr, np.array([1.0, 0, 0, 0, -0.5]))
+    assert st == 2
+
+
+def test_collision_moments_vanish_random_field():
+    pb = wl.sod1d(nelem=3, order=2, nv1=16)
+    pr = from_dict(pb)
+    x = orc.node_coords(pr)
+    f = orc.maxwellian(pr, wl.prim_sod(x)) * wl.perturbation(3, (pr.ne, pr.ns, pr.nv), 0.2)
+    Cc, d = orc.collision(pr, f)
+    u, w = orc.velocity_grid(pr)
+    psi = np.column_stack([np.ones(len(u)), u, 0.5 * (u * u).sum(1)])
+    Cm = Cc.reshape(pr.nx, pr.nv) @ (w[:, None] * psi)
+    Q = orc.moments(pr, f)
+    tau = pr.mu_ref / ((2 / 3) * (Q[:, 4] - 0.5 * (Q[:, 1:4] ** 2).sum(1) / Q[:, 0]))
+    rel = np.abs(Cm * tau[:, None]) / np.column_stack([Q[:, 0]] * 4 + [Q[:, 4]])
+    assert rel.max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Homogeneous relaxation: SSP-RK3 on C alone has a closed form
+# --------------------------------------------------------------------------
+
+def test_rk3_homogeneous_relaxation_closed_form():
+    """Spatially uniform f: transport vanishes, the discrete moments are conserved,
+    so g and tau stay fixed and one step gives f1 - g = R(-dt/tau)(f0 - g) with
+    R(z) = 1 + z + z^2/2 + z^3/6 (three-stage, third-order SSP-RK). g comes from an
+    independent convex-dual solve."""
+    pr = P(nelem=(2,), order=1, nvel=(16,) * 3, vlo=(-6.0,) * 3, vhi=(6.0,) * 3, mu_ref=2e-3,
+           limiter=0)
+    prim = np.tile([1.0, 0.1, 0.0, -0.05, 1.1], (pr.nx, 1))
+    f0 = orc.maxwellian(pr, prim)
+    f0 = f0 * wl.perturbation(11, (1, 1, pr.nv), 0.3)  # same perturbation at every node
+    u, w = orc.velocity_grid(pr)
+    Q = orc.moments(pr, f0)[0]
+    psi = np.column_stack([np.ones(len(u)), u, 0.5 * (u * u).sum(1)])
+    _, a0, _, _ = orc.newton_node(pr, Q)
+    g = np.exp(psi @ _dual_alpha(u, w, Q, a0 * (1 + 1e-4)))
+    Pp = (2.0 / 3.0) * (Q[4] - 0.5 * Q[1:4] @ Q[1:4] / Q[0])
+    tau = pr.mu_ref / Pp
+    dt = 1.3 * tau
+    f1, _ = orc.rk3_step(pr, f0, dt, 2)
+    z = -dt / tau
+    R = 1 + z + z * z / 2 + z ** 3 / 6
+    expect = g + R * R * (f0[0, 0] - g)
+    err = np.abs(f1 - expect[None, None, :]).max() / np.abs(f0).max()
+    assert err < 1e-11
+
+
+# --------------------------------------------------------------------------
+# Transport (Sec. 2.1, FR + upwind flux)
+# --------------------------------------------------------------------------
+
+def _no_coll(**kw):
+    return P(mu_ref=0.0, limiter=0, **kw)
+
+
+def test_transport_of_uniform_state_vanishes():
+    pr = _no_coll(dim=2, order=3, nelem=(3, 2), xlo=(0, 0), xhi=(1, 2), bc=((0, 0), (0, 0)))
+    f = np.tile(wl.perturbation(5, (1, 1, pr.nv), 0.5), (pr.ne, pr.ns, 1))
+    T = orc.transport(pr, f)
+    assert np.abs(T).max() < 1e-12
+
+
+def _dg_weak_form_1d(p, h, a, f_own, f_left_nbr, f_right_nbr):
+    """Independent nodal-DG operator in strong form with exact integrals:
+    M df/dt = -S (a f) + phi(1)(a f_R - H_R) - phi(-1)(a f_L - H_L)."""
+    xi, _ = npleg.leggauss(p + 1)
+    basis = []
+    for b in range(p + 1):
+        others = np.delete(xi, b)
+        c = np.poly1d(others, r=True) / np.prod(xi[b] - others)
+        basis.append(c)
+    qx, qw = npleg.leggauss(2 * p + 4)
+    Mref = np.array([[np.sum(qw * basis[i](qx) * basis[j](qx)) for j in range(p + 1)]
+                     for i in range(p + 1)])
+    S = np.array([[np.sum(qw * basis[i](qx) * basis[j].deriv()(qx)) for j in range(p + 1)]
+                  for i in range(p + 1)])
+    at = lambda v, x0: sum(v[b] * basis[b](x0) for b in range(p + 1))
+    phiR = np.array([basis[i](1.0) for i in range(p + 1)])
+    phiL = np.array([basis[i](-1.0) for i in range(p + 1)])
+    fL, fR = at(f_own, -1.0), at(f_own, 1.0)
+    HL = a * at(f_left_nbr, 1.0) if a > 0 else a * fL
+    HR = a * fR if a > 0 else a * at(f_right_nbr, -1.0)
+    rhs = -(S @ (a * f_own)) + phiR * (a * fR - HR) - phiL * (a * fL - HL)
+    return -np.linalg.solve(Mref * (h / 2.0), rhs)  # T = -df/dt
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4])
+def test_transport_equals_nodal_dg_weak_form(p):
+    pr = _no_coll(order=p, nelem=(3,), xhi=(1.5,))
+    u, _ = orc.velocity_grid(pr)
+    f = wl.perturbation(p + 20, (pr.ne, pr.ns, pr.nv), 0.9)
+    T = orc.transport(pr, f)
+    h = 0.5
+    for e in range(3):
+        for j in [0, 3, 4, 7, 19]:
+            a = u[j, 0]
+            ref = _dg_weak_form_1d(p, h, a, f[e, :, j], f[(e - 1) % 3, :, j], f[(e + 1) % 3, :, j])
+            assert np.max(np.abs(T[e, :, j] - ref)) < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+def test_transport_conservative_and_energy_stable():
+    pr = _no_coll(dim=2, order=2, nelem=(3, 4), xlo=(0, 0), xhi=(1, 1), bc=((0, 0), (0, 0)))
+    f = wl.perturbation(9, (pr.ne, pr.ns, pr.nv), 0.9)
+    T = orc.transport(pr, f)
+    _, wq = orc.gauss_legendre(3)
+    W = np.outer(wq, wq).ravel()  # node i = a1 + 3 a2 (symmetric anyway)
+    tot = np.einsum("i,eij->j", W, T)
+    assert np.abs(tot).max() < 1e-12 * np.abs(T).max()
+    energy = np.einsum("i,eij,eij->j", W, f, T)  # -0.5 d/dt ||f||^2
+    assert energy.min() > -1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_free_streaming_order(p):
+    """Collisionless transport of f0(x - u t, u) (exact solution) converges at order p+1."""
+    errs = []
+    for ne in (6, 12):
+        pr = _no_coll(order=p, nelem=(ne,), nvel=(4, 2, 2), vlo=(-1.5, -1, -1), vhi=(1.5, 1, 1))
+        x = orc.node_coords(pr)[:, 0]
+        u, _ = orc.velocity_grid(pr)
+        f0 = lambda xx: 1.0 + 0.3 * np.sin(2 * math.pi * xx)
+        f = np.stack([f0(x - 0.0 * u[j, 0]) for j in range(pr.nv)], axis=1).reshape(
+            pr.ne, pr.ns, pr.nv)
+        t_end, h = 0.2, 1.0 / ne
+        n = int(math.ceil(t_end / (0.02 * h / 1.5)))
+        f, _ = orc.rk3_step(pr, f, t_end / n, n)
+        ex = np.stack([f0(x - t_end * u[j, 0]) for j in range(pr.nv)], axis=1).reshape(f.shape)
+        _, wq = orc.gauss_legendre(p + 1)
+        errs.append(math.sqrt(np.einsum("i,eij->", wq, (f - ex) ** 2) * h / 2))
+    order = math.log(errs[0] / errs[1], 2)
+    assert order > p + 1 - 0.35, (errs, order)
+
+
+# --------------------------------------------------------------------------
+# Limiter (Sec. 2.1, Zhang-Shu)
+# --------------------------------------------------------------------------
+
+def test_limiter_properties():
+    pr = P(dim=2, order=2, nelem=(2, 2), xlo=(0, 0), xhi=(1, 1), bc=((0, 0), (0, 0)))
+    rng = np.random.default_rng(1)
+    f = rng.uniform(-0.3, 1.0, size=(pr.ne, pr.ns, pr.nv))
+    f[0, :, 0] = -0.2  # slice with negative mean
+    _, wq = orc.gauss_legendre(3)
+    W = np.outer(wq, wq).ravel()
+    g, d = orc.limiter(pr, f)
+    mean = lambda a: np.einsum("i,eij->ej", W, a) / W.sum()
+    assert np.abs(mean(g) - mean(f)).max() < 1e-15
+    pos = mean(f) > 0
+    assert g.min(axis=1)[pos].min() > -1e-15
+    untouched = f.min(axis=1) >= 0
+    assert np.array_equal(g.transpose(0, 2, 1)[untouched], f.transpose(0, 2, 1)[untouched])
+    g2, d2 = orc.limiter(pr, g)
+    assert np.abs(g2 - g)[pos[:, None, :].repeat(pr.ns, 1)].max() < 1e-15
+    assert d["limiter_bad"] >= 1 and d["limiter_hits"] >= d["limiter_bad"]
+
+
+# --------------------------------------------------------------------------
+# Full scheme invariants
+# --------------------------------------------------------------------------
+
+def _totals(pr, f):
+    Q = orc.moments(pr, f).reshape(pr.ne, pr.ns, 5)
+    _, wq = orc.gauss_legendre(pr.order + 1)
+    W = wq
+    for _ in range(pr.dim - 1):
+        W = np.outer(W, wq).ravel()
+    return np.einsum("i,eim->m", W, Q)
+
+
+def test_periodic_run_conserves_totals():
+    pb = wl.box2d(n=3, order=2, nv1=12, kn=5e-3)
+    pr = from_dict(pb)
+    f = orc.maxwellian(pr, wl.prim_box2d(orc.node_coords(pr), amp=0.2))
+    f *= wl.perturbation(2, f.shape, 0.1)
+    t0 = _totals(pr, f)
+    dt = orc.stable_dt(pr, f, 0.1)
+    f1, d = orc.rk3_step(pr, f, dt, 3)
+    t1 = _totals(pr, f1)
+    scale = np.array([t0[0], t0[0], t0[0], t0[0], t0[4]])
+    assert np.max(np.abs(t1 - t0) / scale) < 1e-13
+    assert d["newton_fail"] == 0
+
+
+def test_specular_walls_conserve_mass_and_energy():
+    pb = wl.sod1d(nelem=6, order=2, nv1=8)
+    pr = from_dict(pb)
+    f = orc.maxwellian(pr, wl.prim_sod(orc.node_coords(pr)))
+    t0 = _totals(pr, f)
+    dt = orc.stable_dt(pr, f, 0.1)
+    f1, d = orc.rk3_step(pr, f, dt, 5)
+    t1 = _totals(pr, f1)
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-13
+    assert abs(t1[4] - t0[4]) / t0[4] < 1e-13
+    # transverse momentum stays zero by symmetry of the velocity grid
+    assert np.abs(t1[2:4]).max() < 1e-13
