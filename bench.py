@@ -1,0 +1,189 @@
+"""Throughput benchmark of the BGK phase-space hot path on one MI355X.
+
+One step = one full SSP-RK3 step (three residual evaluations with the fused
+stage kernel, three equilibrium solves) of the whole phase space, inputs
+resident in HBM. Default workload: the 2-D periodic box (32x32 elements,
+p=3, 24^3 velocities on [-6,6]^3, Kn=1e-3; 226,492,416 phase-space DOF), run
+in FP64 and with FP32 bulk storage / FP64 collision side by side.
+
+Prints one JSON line: value = FP64 DOF-updates/s; "mixed" holds the FP32-bulk
+path; "roofline" the dominant kernel (fused stage) against HBM peak;
+"cpu_baseline" the FP64 oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "phase-space DOF-updates/s FP64 vs mixed; p50/p99 latency of batched solves"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def workload(name):
+    from paper_2308_06196_amd import workloads as wl
+    if name == "box2d":
+        return wl.box2d(), wl.prim_box2d, ("box2d: 2-D periodic box [0,1]^2, 32x32 elements p=3, "
+                                           "24^3 velocities on [-6,6]^3, Kn=1e-3, SSP-RK3, CFL 0.1")
+    if name == "sod1d":
+        return wl.sod1d(), wl.prim_sod, ("sod1d: shock tube, 32 elements p=2, 16^3 velocities on "
+                                         "[-6,6]^3, Kn=1e-2, specular walls, SSP-RK3, CFL 0.1")
+    if name == "tgv3d":
+        return wl.tgv3d(), wl.prim_tgv3d, ("tgv3d: 3-D periodic Taylor-Green box, 16^3 elements "
+                                           "p=3, 16^3 velocities on [-5,5]^3, Kn=1e-3")
+    if name == "mach2":
+        return wl.mach2(), wl.prim_mach2, ("mach2: 3-D periodic box, 32^3 elements p=2, 20^3 "
+                                           "velocities on [-8,8]^3, Kn=1e-2, Mach 2")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2308_06196_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def run_gpu(pb, prim_fn, precision, steps, warmup):
+    import torch
+
+    from paper_2308_06196_amd import bgk
+    s = bgk.Solver(pb, precision=precision, device="cuda:0")
+    s.set_maxwellian(prim_fn(s.node_coords()))
+    dt = s.stable_dt(0.1)
+    if warmup:
+        s.rk3_step(dt, warmup)
+    s.synchronize()
+    s.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.rk3_step(dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = s.timing_read()
+    s.timing(False)
+    diag = s.diagnostics()
+    dof = s.nx * s.nv
+    out = {"dof": dof, "elapsed_s": el, "ms_per_step": 1e3 * el / steps,
+           "value": dof * steps / el, "timing": tm, "diag": diag, "dt": dt,
+           "bytes_per_value": 8 if precision == 0 else 4}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(res, steps):
+    """Fused stage kernel: algorithmic bytes = compulsory f traffic, 2s (stage 1:
+    read input, write output) + 3s + 3s (stages 2, 3: also read f^n) per DOF,
+    i.e. 8s/3 per DOF per launch on average."""
+    tm = res["timing"]
+    n = tm["stage_launches"]
+    if not n:
+        return None
+    avg_ms = tm["stage_ms"] / n
+    bytes_per_launch = 8.0 * res["bytes_per_value"] * res["dof"] / 3.0
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        tr = json.load(open(TRAFFIC_FILE))
+        key = f"stage_{'f64' if res['bytes_per_value'] == 8 else 'f32'}"
+        if tr.get("source_hash") == kernel_source_hash() and key in tr:
+            traffic = tr[key]["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_stage (fused FR transport + BGK relaxation + SSP-RK combine + limiter "
+                      "+ moment partials)",
+            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def cpu_baseline(pb_full, prim_fn, budget_s=12.0):
+    """FP64 oracle (plain, untuned) on the same workload restricted to an 8x8-element
+    box (same p, velocity grid, IC and Kn); DOF-updates/s over as many steps as fit
+    in about budget_s seconds."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2308_06196_amd import workloads as wl  # noqa: F401
+    keys = ["dim", "order", "nelem", "xlo", "xhi", "nvel", "vlo", "vhi", "bc", "mu_ref",
+            "theta_ref", "omega", "gamma", "limiter", "newton_maxit", "newton_tol"]
+    pb = dict(pb_full)
+    d = pb["dim"]
+    pb["nelem"] = [min(8, n) if k < d else 1 for k, n in enumerate(pb["nelem"])]
+    pr = orc.Problem(**{k: pb[k] for k in keys})
+    f = orc.maxwellian(pr, prim_fn(orc.node_coords(pr)))
+    dt = orc.stable_dt(pr, f, 0.1)
+    t0 = time.perf_counter()
+    f, _ = orc.rk3_step(pr, f, dt, 1)
+    t1 = time.perf_counter() - t0
+    more = max(0, int(budget_s / max(t1, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    if more:
+        f, _ = orc.rk3_step(pr, f, dt, more)
+    t2 = time.perf_counter() - t0
+    steps = 1 + more
+    dof = pr.nx * pr.nv
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": dof * steps / (t1 + t2), "unit": "DOF-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{'x'.join(str(n) for n in pb['nelem'][:d])} elements of the same workload "
+                      f"({dof} DOF), {steps} SSP-RK3 steps, {t1 + t2:.1f} s, FP64, "
+                      f"direct velocity sums"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="box2d")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the headline value")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+    pb, prim_fn, desc = workload(a.workload)
+    main_prec = 0 if a.precision == "fp64" else 1
+    res = run_gpu(pb, prim_fn, main_prec, a.steps, a.warmup)
+    print(f"[bench] {a.workload} {a.precision}: {res['value']:.4e} DOF-updates/s, "
+          f"{res['ms_per_step']:.3f} ms/step, timing {res['timing']}", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC, "value": res["value"], "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if main_prec == 0 else "f32-bulk/f64-collision", "data": "synthetic",
+        "config": {"workload": desc, "dof": res["dof"], "dt": res["dt"],
+                   "newton_it_max": res["diag"]["newton_it_max"],
+                   "limiter_hits": res["diag"]["limiter_hits"]},
+        "roofline": roofline(res, a.steps),
+    }
+    if not a.no_mixed and main_prec == 0:
+        mx = run_gpu(pb, prim_fn, 1, a.steps, a.warmup)
+        print(f"[bench] {a.workload} fp32-bulk: {mx['value']:.4e} DOF-updates/s, "
+              f"{mx['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        line["mixed"] = {"dtype": "f32-bulk/f64-collision", "value": mx["value"],
+                         "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps)}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pb, prim_fn)
+        print(f"[bench] cpu baseline {line['cpu_baseline']}", file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+"""Thin ctypes binding of libbgk (C-ABI declared in include/bgk.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of libbgk.so. PyTorch provides device memory (the solver workspace
+and exchange buffers) and the stream. There is no fallback: if the library
+is missing or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbgk.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bgk.h")
+
+BGK_OK = 0
+BGK_HOST, BGK_DEVICE = 0, 1
+FP64, FP32 = 0, 1
+STATUS = {0: "BGK_OK", 1: "BGK_ERR_INVALID_ARG", 2: "BGK_ERR_UNSUPPORTED",
+          3: "BGK_ERR_OUT_OF_MEMORY", 4: "BGK_ERR_DEVICE", 5: "BGK_ERR_NEWTON",
+          6: "BGK_ERR_NONFINITE", 7: "BGK_ERR_STATE"}
+
+
+class BGKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("order", C.c_int32),
+        ("nelem", C.c_int32 * 3),
+        ("xlo", C.c_double * 3), ("xhi", C.c_double * 3),
+        ("bc", (C.c_int32 * 2) * 3),
+        ("nvel", C.c_int32 * 3),
+        ("vlo", C.c_double * 3), ("vhi", C.c_double * 3),
+        ("mu_ref", C.c_double), ("theta_ref", C.c_double), ("omega", C.c_double),
+        ("gamma", C.c_double),
+        ("precision", C.c_int32), ("limiter", C.c_int32),
+        ("newton_maxit", C.c_int32),
+        ("newton_tol", C.c_double),
+    ]
+
+
+class Timing(C.Structure):
+    _fields_ = [("stage_launches", C.c_int64), ("stage_ms", C.c_double),
+                ("newton_launches", C.c_int64), ("newton_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if k.endswith("ms") else int(getattr(self, k)))
+                for k, _ in self._fields_}
+
+
+class Diag(C.Structure):
+    _fields_ = [("newton_it_max", C.c_int64), ("newton_fail", C.c_int64),
+                ("limiter_hits", C.c_int64), ("limiter_bad", C.c_int64),
+                ("stages", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def problem_struct(pb: dict, precision: int = FP64) -> Problem:
+    """bgk_problem from a plain problem dict (see workloads.problem)."""
+    s = Problem()
+    s.dim, s.order = int(pb["dim"]), int(pb["order"])
+    for k in range(3):
+        s.nelem[k] = int(pb["nelem"][k])
+        s.xlo[k], s.xhi[k] = float(pb["xlo"][k]), float(pb["xhi"][k])
+        s.bc[k][0], s.bc[k][1] = int(pb["bc"][k][0]), int(pb["bc"][k][1])
+        s.nvel[k] = int(pb["nvel"][k])
+        s.vlo[k], s.vhi[k] = float(pb["vlo"][k]), float(pb["vhi"][k])
+    s.mu_ref, s.theta_ref = float(pb["mu_ref"]), float(pb["theta_ref"])
+    s.omega, s.gamma = float(pb["omega"]), float(pb["gamma"])
+    s.precision, s.limiter = int(precision), int(pb["limiter"])
+    s.newton_maxit, s.newton_tol = int(pb["newton_maxit"]), float(pb["newton_tol"])
+    return s
+
+
+_lib = None
+
+
+def exported_names() -> list:
+    """Function names declared in include/bgk.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:bgk_status|const char\*)\s+(bgk_\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int32
+        pp = C.POINTER(Problem)
+        sig = {
+            "bgk_query_footprint": [pp, C.POINTER(C.c_size_t), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)],
+            "bgk_create": [pp, vp, C.c_size_t, vp, C.POINTER(vp)],
+            "bgk_destroy": [vp],
+            "bgk_node_coords": [vp, dp],
+            "bgk_velocity_grid": [vp, dp, dp],
+            "bgk_set_state": [vp, vp, i32],
+            "bgk_set_maxwellian": [vp, vp, i32],
+            "bgk_get_state": [vp, vp, i32],
+            "bgk_residual": [vp, vp, vp, i32],
+            "bgk_rk3_step": [vp, C.c_double, i32],
+            "bgk_moments": [vp, vp, i32],
+            "bgk_stable_dt": [vp, C.c_double, dp],
+            "bgk_diagnostics": [vp, C.POINTER(Diag)],
+            "bgk_synchronize": [vp],
+            "bgk_timing_enable": [vp, i32],
+            "bgk_timing_read": [vp, C.POINTER(Timing)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.bgk_status_str.argtypes = [C.c_int]
+        L.bgk_status_str.restype = C.c_char_p
+        L.bgk_last_error.argtypes = []
+        L.bgk_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != BGK_OK:
+        raise BGKError(st, lib().bgk_last_error().decode())
+
+
+def footprint(pb: dict, precision: int = FP64):
+    s = problem_struct(pb, precision)
+    b, nx, nv = C.c_size_t(0), C.c_int64(0), C.c_int64(0)
+    _check(lib().bgk_query_footprint(C.byref(s), C.byref(b), C.byref(nx), C.byref(nv)))
+    return int(b.value), int(nx.value), int(nv.value)
+
+
+class Solver:
+    """One problem instance on one GPU. The workspace is a torch uint8 tensor
+    owned by this object; the stream defaults to torch's current stream."""
+
+    def __init__(self, pb: dict, precision: int = FP64, device="cuda:0", stream=None,
+                 workspace=None):
+        import torch
+
+        self.torch = torch
+        self.pb = pb
+        self.precision = precision
+        self.device = torch.device(device)
+        nbytes, self.nx, self.nv = footprint(pb, precision)
+        self.ne = int(np.prod(pb["nelem"][: pb["dim"]]))
+        self.ns = (pb["order"] + 1) ** pb["dim"]
+        self.workspace_bytes = nbytes
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        assert workspace.numel() >= nbytes and workspace.data_ptr() % 256 == 0
+        self.workspace = workspace
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._s = C.c_void_p()
+        st = problem_struct(pb, precision)
+        _check(lib().bgk_create(C.byref(st), C.c_void_p(workspace.data_ptr()), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(self._s)))
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if self._s:
+            lib().bgk_destroy(self._s)
+            self._s = C.c_void_p()
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------
+    @property
+    def shape(self):
+        return (self.ne, self.ns, self.nv)
+
+    def _arg(self, a, n: int):
+        """(pointer, where, keepalive) for a float64 array of n values."""
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            assert a.dtype == torch.float64 and a.is_contiguous() and a.numel() == n
+            if a.is_cuda:
+                return C.c_void_p(a.data_ptr()), BGK_DEVICE, a
+            a = a.numpy()
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        assert a.size == n
+        return C.c_void_p(a.ctypes.data), BGK_HOST, a
+
+    # -- C-ABI wrappers ----------------------------------------------------------
+    def node_coords(self) -> np.ndarray:
+        x = np.zeros((self.nx, self.pb["dim"]))
+        _check(lib().bgk_node_coords(self._s, x.ctypes.data_as(C.POINTER(C.c_double))))
+        return x
+
+    def velocity_grid(self):
+        u, w = np.zeros((self.nv, 3)), np.zeros(self.nv)
+        _check(lib().bgk_velocity_grid(self._s, u.ctypes.data_as(C.POINTER(C.c_double)),
+                                       w.ctypes.data_as(C.POINTER(C.c_double))))
+        return u, w
+
+    def set_state(self, f):
+        p, where, keep = self._arg(f, self.nx * self.nv)
+        _check(lib().bgk_set_state(self._s, p, where))
+        return keep
+
+    def set_maxwellian(self, prim):
+        p, where, keep = self._arg(prim, self.nx * 5)
+        _check(lib().bgk_set_maxwellian(self._s, p, where))
+        return keep
+
+    def get_state(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        p, where, keep = self._arg(out, self.nx * self.nv)
+        _check(lib().bgk_get_state(self._s, p, where))
+        return out if where == BGK_DEVICE or isinstance(out, torch.Tensor) else keep
+
+    def residual(self, f_in=None, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        po, where, keep_o = self._arg(out, self.nx * self.nv)
+        pi = None
+        keep_i = None
+        if f_in is not None:
+            pi, where_i, keep_i = self._arg(f_in, self.nx * self.nv)
+            assert where_i == where, "f_in and out must both be host or both device"
+        _check(lib().bgk_residual(self._s, pi, po, where))
+        return out if isinstance(out, torch.Tensor) else keep_o
+
+    def rk3_step(self, dt: float, nsteps: int = 1):
+        _check(lib().bgk_rk3_step(self._s, float(dt), int(nsteps)))
+
+    def moments(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.nx, 5), dtype=torch.float64, device=self.device)
+        p, where, keep = self._arg(out, self.nx * 5)
+        _check(lib().bgk_moments(self._s, p, where))
+        return out if isinstance(out, torch.Tensor) else keep
+
+    def stable_dt(self, cfl: float) -> float:
+        dt = C.c_double(0.0)
+        _check(lib().bgk_stable_dt(self._s, float(cfl), C.byref(dt)))
+        return float(dt.value)
+
+    def diagnostics(self, raise_on_failure: bool = True) -> dict:
+        d = Diag()
+        st = lib().bgk_diagnostics(self._s, C.byref(d))
+        if raise_on_failure:
+            _check(st)
+        return d.as_dict()
+
+    def synchronize(self):
+        _check(lib().bgk_synchronize(self._s))
+
+    def timing(self, on: bool):
+        _check(lib().bgk_timing_enable(self._s, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        t = Timing()
+        _check(lib().bgk_timing_read(self._s, C.byref(t)))
+        return t.as_dict()

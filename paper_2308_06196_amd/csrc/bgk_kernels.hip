@@ -1,0 +1,314 @@
+// bgk_kernels.hip -- kernel instantiations and launchers (gfx950).
+//
+// Kernels: the fused stage (transport + relaxation + RK + limiter + moment
+// partials), the residual, stand-alone moment partials, the per-node Newton
+// solve for the discretely conservative equilibrium, and state conversion /
+// Maxwellian initialisation. All launched on the caller's stream.
+#include "bgk_device.hpp"
+#include "bgk_launch.hpp"
+
+namespace bgk {
+
+// ---------------------------------------------------------------------------
+// Discretely conservative equilibrium, one thread per spatial node
+// (Sec. 2.1: Maxwellian on a perturbed state whose discrete moments equal
+// those of f; Newton's method with the closed-form Jacobian).
+//
+// g_j = exp(alpha . psi_j) and the trapezoid weights are products over the
+// three velocity components, so every sum over the N_v nodes factorises into
+// one-dimensional sums S_c^n = sum_b w_c[b] E_c[b] u_b^n (n = 0..4) with
+// E_c[b] = exp(alpha_{1+c} u_b + alpha_4 u_b^2 / 2): O(3 N_1d) work per node.
+// ---------------------------------------------------------------------------
+__device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
+  double L[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) L[i][k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int k = 0; k <= i; ++k) {
+      double s = J[i][k];
+#pragma unroll
+      for (int m = 0; m < k; ++m) s -= L[i][m] * L[k][m];
+      if (i == k) {
+        if (!(s > 0.0)) return 1;
+        L[i][i] = sqrt(s);
+      } else {
+        L[i][k] = s / L[k][k];
+      }
+    }
+  }
+  double y[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double s = b[i];
+#pragma unroll
+    for (int m = 0; m < i; ++m) s -= L[i][m] * y[m];
+    y[i] = s / L[i][i];
+  }
+#pragma unroll
+  for (int i = 4; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int m = i + 1; m < 5; ++m) s -= L[m][i] * x[m];
+    x[i] = s / L[i][i];
+  }
+  return 0;
+}
+
+__global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
+  const DevGeom& g = A.g;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= g.nx) return;
+  double Q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double* pp = A.partials + node * g.nchunk * 5;
+  for (int c = 0; c < g.nchunk; ++c)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Q[m] += pp[c * 5 + m];
+  if (A.Q) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) A.Q[node * 5 + m] = Q[m];
+  }
+  double* out = A.params + node * 8;
+  if (!A.collide) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) out[m] = 0.0;
+    return;
+  }
+  const double rho = Q[0];
+  const double UU = (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]) / (rho * rho);
+  const double P = (A.gamma - 1.0) * (Q[4] - 0.5 * rho * UU);
+  const double th = P / rho;
+  int status = 0, iters = 0;
+  double al[5];
+  if (!(rho > 0.0) || !(th > 0.0)) {
+    status = 2;
+  } else {
+    al[0] = log(rho / pow(2.0 * M_PI * th, 1.5)) - UU / (2.0 * th);
+    al[1] = Q[1] / rho / th;
+    al[2] = Q[2] / rho / th;
+    al[3] = Q[3] / rho / th;
+    al[4] = -1.0 / th;
+    const double sq = rho * sqrt(th);
+    const double sc[5] = {rho, sq, sq, sq, Q[4]};
+    for (int it = 0;; ++it) {
+      double S[3][5];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int n = 0; n < 5; ++n) S[c][n] = 0.0;
+        const int N = g.nv1[c];
+        for (int b = 0; b < N; ++b) {
+          const double u = g.vlo[c] + b * g.du[c];
+          double wc = g.du[c];
+          if (b == 0 || b == N - 1) wc *= 0.5;
+          const double t = wc * exp(al[1 + c] * u + al[4] * (0.5 * u * u));
+          const double u2 = u * u;
+          S[c][0] += t;
+          S[c][1] += t * u;
+          S[c][2] += t * u2;
+          S[c][3] += t * u2 * u;
+          S[c][4] += t * u2 * u2;
+        }
+      }
+      double m[3][5];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int n = 0; n < 5; ++n) m[c][n] = S[c][n] / S[c][0];
+      const double A0 = exp(al[0]) * S[0][0] * S[1][0] * S[2][0];
+      double G[5], J[5][5];
+      G[0] = A0;
+      G[1] = A0 * m[0][1];
+      G[2] = A0 * m[1][1];
+      G[3] = A0 * m[2][1];
+      G[4] = A0 * 0.5 * (m[0][2] + m[1][2] + m[2][2]);
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        J[0][a] = G[a];
+        J[a][0] = G[a];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2)
+          J[1 + c][1 + c2] = (c == c2) ? A0 * m[c][2] : A0 * m[c][1] * m[c2][1];
+        double t = m[c][3];
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2)
+          if (c2 != c) t += m[c][1] * m[c2][2];
+        J[1 + c][4] = J[4][1 + c] = A0 * 0.5 * t;
+      }
+      J[4][4] = A0 * 0.25 *
+                (m[0][4] + m[1][4] + m[2][4] +
+                 2.0 * (m[0][2] * m[1][2] + m[0][2] * m[2][2] + m[1][2] * m[2][2]));
+      double F[5], r = 0.0;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        F[a] = G[a] - Q[a];
+        const double ra = fabs(F[a]) / sc[a];
+        if (!(ra <= r)) r = ra;
+      }
+      iters = it + 1;
+      const bool conv = r <= A.tol;
+      if (!conv && it >= A.maxit) {
+        status = 1;
+        break;
+      }
+      double d[5];
+      if (chol5_solve(J, F, d)) {
+        status = 2;
+        break;
+      }
+      double an[5];
+#pragma unroll
+      for (int a = 0; a < 5; ++a) an[a] = al[a] - d[a];
+      for (int h = 0; h < 60 && !(an[4] < 0.0); ++h) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+          d[a] *= 0.5;
+          an[a] = al[a] - d[a];
+        }
+      }
+      if (!(an[4] < 0.0)) {
+        status = 2;
+        break;
+      }
+#pragma unroll
+      for (int a = 0; a < 5; ++a) al[a] = an[a];
+      if (conv) break;  // that was the polishing step
+    }
+  }
+  if (status) {
+#pragma unroll
+    for (int a = 0; a < 5; ++a) al[a] = __builtin_nan("");
+    atomicAdd(&A.diag[1], 1ull);
+  }
+  const double mu = A.mu_ref * pow(th / A.theta_ref, A.omega);
+  const double tau = mu / P;
+#pragma unroll
+  for (int a = 0; a < 5; ++a) out[a] = al[a];
+  out[5] = 1.0 / tau;
+  out[6] = tau;
+  out[7] = (double)status;
+  atomicMax(&A.diag[0], (unsigned long long)iters);
+}
+
+// Q[node][5] from the partials (no Newton solve).
+__global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const double* partials,
+                                                         double* Q) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= g.nx) return;
+  double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double* pp = partials + node * g.nchunk * 5;
+  for (int c = 0; c < g.nchunk; ++c)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) q[m] += pp[c * 5 + m];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Q[node * 5 + m] = q[m];
+}
+
+// Continuous Maxwellian sampled at every (node, velocity); one work-group =
+// one node x one velocity chunk.
+template <typename ST>
+__global__ void __launch_bounds__(kBlock) k_maxwellian(const DevGeom g, const double* prim, ST* f) {
+  const int64_t w = blockIdx.x;
+  const int64_t node = w / g.nchunk;
+  const int chunk = (int)(w % g.nchunk);
+  const int64_t j = (int64_t)chunk * kBlock + threadIdx.x;
+  if (j >= g.nv) return;
+  const Vel v = velocity_of(g, j);
+  const double* q = prim + node * 5;
+  const double rho = q[0], th = q[4];
+  const double nrm = rho / pow(2.0 * M_PI * th, 1.5);
+  const double dx = v.u[0] - q[1], dy = v.u[1] - q[2], dz = v.u[2] - q[3];
+  f[node * g.nv + j] = (ST)(nrm * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * th)));
+}
+
+template <typename SRC, typename DST>
+__global__ void __launch_bounds__(256) k_convert(const SRC* in, DST* out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = (DST)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename ST>
+static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
+  const dim3 grid((unsigned)(A.g.nchunk * A.ecount)), block(kBlock);
+  const int key = A.g.dim * 10 + (A.g.n1 - 1);
+#define BGK_CASE(D, P)                                                     \
+  case D * 10 + P:                                                         \
+    if (mode == 0)                                                         \
+      hipLaunchKernelGGL((k_stage<D, P, ST, 0>), grid, block, 0, s, A);    \
+    else if (mode == 1)                                                    \
+      hipLaunchKernelGGL((k_stage<D, P, ST, 1>), grid, block, 0, s, A);    \
+    else                                                                   \
+      hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, 0, s, A);     \
+    break;
+  switch (key) {
+    BGK_CASE(1, 1) BGK_CASE(1, 2) BGK_CASE(1, 3)
+    BGK_CASE(2, 1) BGK_CASE(2, 2) BGK_CASE(2, 3)
+    BGK_CASE(3, 1) BGK_CASE(3, 2) BGK_CASE(3, 3)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef BGK_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s) {
+  if (A.ecount <= 0) return hipSuccess;
+  return precision == 0 ? stage_dispatch<double>(mode, A, s) : stage_dispatch<float>(mode, A, s);
+}
+
+hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_newton, dim3(grid_of(A.g.nx, 256)), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(grid_of(g.nx, 256)), dim3(256), 0, s, g, partials,
+                     Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,
+                             hipStream_t s) {
+  const dim3 grid((unsigned)(g.nx * g.nchunk));
+  if (precision == 0)
+    hipLaunchKernelGGL(k_maxwellian<double>, grid, dim3(kBlock), 0, s, g, prim, (double*)f);
+  else
+    hipLaunchKernelGGL(k_maxwellian<float>, grid, dim3(kBlock), 0, s, g, prim, (float*)f);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_storage(int precision, const double* in, void* out, int64_t n,
+                             hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>(grid_of(n, 256), 65536);
+  if (precision == 0) {
+    return hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(grid), dim3(256), 0, s, in, (float*)out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_storage(int precision, const void* in, double* out, int64_t n,
+                               hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>(grid_of(n, 256), 65536);
+  if (precision == 0) {
+    return hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(grid), dim3(256), 0, s, (const float*)in,
+                     out, n);
+  return hipGetLastError();
+}
+
+}  // namespace bgk

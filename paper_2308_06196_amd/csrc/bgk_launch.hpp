@@ -1,0 +1,26 @@
+// bgk_launch.hpp -- host-side launch interface between the C-ABI runtime and
+// the gfx950 kernels. Internal to libbgk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "bgk_device.hpp"
+
+namespace bgk {
+
+// mode 0: fused RK stage; 1: residual L(f) in FP64; 2: moment partials only.
+hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s);
+hipError_t launch_newton(const NewtonArgs& A, hipStream_t s);
+hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,
+                                  hipStream_t s);
+hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,
+                             hipStream_t s);
+hipError_t launch_to_storage(int precision, const double* in, void* out, int64_t n,
+                             hipStream_t s);
+hipError_t launch_from_storage(int precision, const void* in, double* out, int64_t n,
+                               hipStream_t s);
+
+}  // namespace bgk

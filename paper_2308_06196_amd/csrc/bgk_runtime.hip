@@ -1,0 +1,764 @@
+// bgk_runtime.hip -- C-ABI runtime of libbgk (declared in include/bgk.h).
+//
+// Host responsibilities: validate the problem, lay out the caller's device
+// workspace, build the FP64 operator tables, sequence the kernels of a
+// residual evaluation or of SSP-RK3 steps on the caller's stream, and move
+// canonical FP64 data in and out. No device memory is allocated here.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bgk.h"
+#include "bgk_launch.hpp"
+
+using namespace bgk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bgk_status fail(bgk_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+bgk_status fail(bgk_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return fail(BGK_ERR_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                             \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------------------
+// One-dimensional operators, built on the host in FP64.
+//
+// Gauss-Legendre rule by the Golub-Welsch construction: the nodes are the
+// eigenvalues of the symmetric tridiagonal Jacobi matrix of the Legendre
+// recurrence (off-diagonal k / sqrt(4k^2 - 1)), the weights are twice the
+// squared first components of the normalised eigenvectors. The small
+// symmetric eigenproblem is solved by cyclic Jacobi rotations.
+// ---------------------------------------------------------------------------
+void gauss_golub_welsch(int n, double* x, double* w) {
+  double A[kMaxN1][kMaxN1] = {}, V[kMaxN1][kMaxN1] = {};
+  for (int i = 0; i < n; ++i) V[i][i] = 1.0;
+  for (int k = 1; k < n; ++k) A[k - 1][k] = A[k][k - 1] = k / sqrt(4.0 * k * k - 1.0);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p][q] * A[p][q];
+    if (off < 1e-34) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- A R
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- R^T A
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // V <- V R
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  int idx[kMaxN1];
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx, idx + n, [&](int a, int b) { return A[a][a] < A[b][b]; });
+  for (int i = 0; i < n; ++i) {
+    const int k = idx[i];
+    double nrm = 0.0;
+    for (int r = 0; r < n; ++r) nrm += V[r][k] * V[r][k];
+    x[i] = A[k][k];
+    w[i] = 2.0 * V[0][k] * V[0][k] / nrm;
+  }
+  // symmetrise (the rule is exactly symmetric about 0)
+  for (int i = 0; i < n / 2; ++i) {
+    const double xm = 0.5 * (x[n - 1 - i] - x[i]), wm = 0.5 * (w[i] + w[n - 1 - i]);
+    x[i] = -xm;
+    x[n - 1 - i] = xm;
+    w[i] = w[n - 1 - i] = wm;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// Barycentric Lagrange tools: weights c_b = 1 / prod_{m != b}(xi_b - xi_m);
+// D_ab = (c_b / c_a) / (xi_a - xi_b) (a != b), D_aa = -sum_{b != a} D_ab;
+// l_b(x) = (c_b / (x - xi_b)) / sum_m (c_m / (x - xi_m)) off the nodes.
+void build_ops(int n1, int dim, DevOps& op) {
+  double xi[kMaxN1], wq[kMaxN1], c[kMaxN1];
+  gauss_golub_welsch(n1, xi, wq);
+  for (int b = 0; b < n1; ++b) {
+    double pr = 1.0;
+    for (int m = 0; m < n1; ++m)
+      if (m != b) pr *= xi[b] - xi[m];
+    c[b] = 1.0 / pr;
+  }
+  memset(&op, 0, sizeof(op));
+  for (int a = 0; a < n1; ++a) {
+    double diag = 0.0;
+    for (int b = 0; b < n1; ++b) {
+      if (a == b) continue;
+      op.D[a][b] = (c[b] / c[a]) / (xi[a] - xi[b]);
+      diag -= op.D[a][b];
+    }
+    op.D[a][a] = diag;
+  }
+  for (int side = 0; side < 2; ++side) {
+    const double x0 = side == 0 ? -1.0 : 1.0;
+    double den = 0.0;
+    for (int m = 0; m < n1; ++m) den += c[m] / (x0 - xi[m]);
+    for (int b = 0; b < n1; ++b) (side == 0 ? op.lamL : op.lamR)[b] = (c[b] / (x0 - xi[b])) / den;
+  }
+  // Correction functions recovering nodal DG: at Gauss points their slopes are
+  // g_L'(xi_a) = -l_a(-1) / w_a and g_R'(xi_a) = l_a(+1) / w_a.
+  for (int a = 0; a < n1; ++a) {
+    op.GL[a] = -op.lamL[a] / wq[a];
+    op.GR[a] = op.lamR[a] / wq[a];
+  }
+  int ns = 1;
+  for (int k = 0; k < dim; ++k) ns *= n1;
+  double ws = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    double Wi = 1.0;
+    int r = i;
+    for (int k = 0; k < dim; ++k) {
+      Wi *= wq[r % n1];
+      r /= n1;
+    }
+    op.W[i] = Wi;
+  }
+  for (int i = 0; i < ns; ++i) ws += op.W[i];
+  op.Wsum = ws;
+}
+
+void gauss_nodes(int n1, double* xi) {
+  double w[kMaxN1];
+  gauss_golub_welsch(n1, xi, w);
+}
+
+struct Layout {
+  size_t f[3], partials, params, Q, prim, diag, total;
+  int64_t nx, nv, ne;
+  int ns, nchunk;
+  size_t fbytes;
+};
+
+bgk_status validate(const bgk_problem* pb) {
+  if (!pb) return fail(BGK_ERR_INVALID_ARG, "problem is NULL");
+  if (pb->dim < 1 || pb->dim > 3) return fail(BGK_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
+  if (pb->order < 1 || pb->order > 3)
+    return fail(BGK_ERR_UNSUPPORTED, "order %d not built (1..3)", pb->order);
+  if (pb->precision != BGK_FP64 && pb->precision != BGK_FP32)
+    return fail(BGK_ERR_INVALID_ARG, "precision must be BGK_FP64 or BGK_FP32");
+  if (pb->limiter != 0 && pb->limiter != 1)
+    return fail(BGK_ERR_INVALID_ARG, "limiter must be 0 or 1");
+  for (int k = 0; k < pb->dim; ++k) {
+    if (pb->nelem[k] < 1) return fail(BGK_ERR_INVALID_ARG, "nelem[%d] < 1", k);
+    if (!(pb->xhi[k] > pb->xlo[k])) return fail(BGK_ERR_INVALID_ARG, "xhi[%d] <= xlo[%d]", k, k);
+    for (int s = 0; s < 2; ++s)
+      if (pb->bc[k][s] != BGK_BC_PERIODIC && pb->bc[k][s] != BGK_BC_SPECULAR)
+        return fail(BGK_ERR_INVALID_ARG, "bc[%d][%d] unknown", k, s);
+    if ((pb->bc[k][0] == BGK_BC_PERIODIC) != (pb->bc[k][1] == BGK_BC_PERIODIC))
+      return fail(BGK_ERR_INVALID_ARG, "axis %d: periodic on one side only", k);
+    if (pb->bc[k][0] == BGK_BC_SPECULAR && pb->vlo[k] != -pb->vhi[k])
+      return fail(BGK_ERR_INVALID_ARG, "specular wall on axis %d needs vlo == -vhi", k);
+  }
+  for (int c = 0; c < 3; ++c) {
+    if (pb->nvel[c] < 2) return fail(BGK_ERR_INVALID_ARG, "nvel[%d] < 2", c);
+    if (!(pb->vhi[c] > pb->vlo[c])) return fail(BGK_ERR_INVALID_ARG, "vhi[%d] <= vlo[%d]", c, c);
+  }
+  if (!(pb->theta_ref > 0.0) && pb->mu_ref > 0.0)
+    return fail(BGK_ERR_INVALID_ARG, "theta_ref must be > 0");
+  return BGK_OK;
+}
+
+Layout layout_of(const bgk_problem* pb) {
+  Layout L;
+  L.ne = 1;
+  for (int k = 0; k < pb->dim; ++k) L.ne *= pb->nelem[k];
+  L.ns = 1;
+  for (int k = 0; k < pb->dim; ++k) L.ns *= pb->order + 1;
+  L.nx = L.ne * L.ns;
+  L.nv = (int64_t)pb->nvel[0] * pb->nvel[1] * pb->nvel[2];
+  L.nchunk = (int)((L.nv + kBlock - 1) / kBlock);
+  const size_t s = pb->precision == BGK_FP64 ? 8 : 4;
+  L.fbytes = (size_t)L.nx * (size_t)L.nv * s;
+  size_t off = 0;
+  for (int b = 0; b < 3; ++b) {
+    L.f[b] = off;
+    off = align_up(off + L.fbytes);
+  }
+  L.partials = off;
+  off = align_up(off + (size_t)L.nx * L.nchunk * 5 * sizeof(double));
+  L.params = off;
+  off = align_up(off + (size_t)L.nx * 8 * sizeof(double));
+  L.Q = off;
+  off = align_up(off + (size_t)L.nx * 5 * sizeof(double));
+  L.prim = off;
+  off = align_up(off + (size_t)L.nx * 5 * sizeof(double));
+  L.diag = off;
+  off = align_up(off + 8 * sizeof(unsigned long long));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct bgk_solver {
+  bgk_problem pb;
+  Layout L;
+  DevGeom g;
+  DevOps op;
+  char* ws;
+  hipStream_t stream;
+  int precision;
+  bool has_state = false;
+  bool partials_valid = false;
+  bool failed = false;
+  bool counters_ready = false;  // device counters cleared since create
+  double gamma;
+  // event timing of rk3_step launches: events[i] .. events[i+1] brackets
+  // interval i of kind kinds[i] (0 newton, 1 stage, 2 host gap)
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<int> kinds;
+  void* f(int b) const { return ws + L.f[b]; }
+  double* partials() const { return (double*)(ws + L.partials); }
+  double* params() const { return (double*)(ws + L.params); }
+  double* Q() const { return (double*)(ws + L.Q); }
+  double* prim() const { return (double*)(ws + L.prim); }
+  unsigned long long* diag() const { return (unsigned long long*)(ws + L.diag); }
+  size_t s_bytes() const { return precision == BGK_FP64 ? 8 : 4; }
+};
+
+namespace {
+
+StageArgs stage_args(const bgk_solver* s) {
+  StageArgs A;
+  memset(&A, 0, sizeof(A));
+  A.g = s->g;
+  A.op = s->op;
+  A.params = s->params();
+  A.partials = s->partials();
+  A.diag = s->diag();
+  A.e0 = 0;
+  A.ecount = s->L.ne;
+  A.out_e0 = 0;
+  A.limiter = s->pb.limiter;
+  A.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
+  return A;
+}
+
+NewtonArgs newton_args(const bgk_solver* s) {
+  NewtonArgs N;
+  memset(&N, 0, sizeof(N));
+  N.g = s->g;
+  N.partials = s->partials();
+  N.params = s->params();
+  N.Q = s->Q();
+  N.diag = s->diag();
+  N.gamma = s->gamma;
+  N.mu_ref = s->pb.mu_ref;
+  N.theta_ref = s->pb.theta_ref;
+  N.omega = s->pb.omega;
+  N.tol = s->pb.newton_tol > 0.0 ? s->pb.newton_tol : 1e-14;
+  N.maxit = s->pb.newton_maxit > 0 ? s->pb.newton_maxit : 20;
+  N.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
+  return N;
+}
+
+// The device counters are cleared by the first call that queues device work
+// (create itself never touches the workspace).
+bgk_status ensure_counters(bgk_solver* s) {
+  if (!s->counters_ready) {
+    HIP_TRY(hipMemsetAsync(s->diag(), 0, 8 * sizeof(unsigned long long), s->stream));
+    s->counters_ready = true;
+  }
+  return BGK_OK;
+}
+
+bgk_status moments_of(bgk_solver* s, const void* fstore) {
+  StageArgs A = stage_args(s);
+  A.fin = fstore;
+  HIP_TRY(launch_stage(s->precision, 2, A, s->stream));
+  return BGK_OK;
+}
+
+bgk_status ensure_partials(bgk_solver* s) {
+  if (!s->partials_valid) {
+    bgk_status st = moments_of(s, s->f(0));
+    if (st) return st;
+    s->partials_valid = true;
+  }
+  return BGK_OK;
+}
+
+bgk_status check_failed(bgk_solver* s) {
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (!s->counters_ready) return BGK_OK;
+  unsigned long long d[8];
+  HIP_TRY(hipMemcpy(d, s->diag(), sizeof(d), hipMemcpyDeviceToHost));
+  if (d[1] > 0) {
+    s->failed = true;
+    return fail(BGK_ERR_NEWTON, "%llu node solve(s) failed (non-realizable moments or Newton "
+                "not converged)", d[1]);
+  }
+  return BGK_OK;
+}
+
+// Copy n FP64 values from host into storage-precision device memory dst,
+// staging through the device scratch region [stage, stage + cap).
+bgk_status host_to_storage(bgk_solver* s, const double* h, void* dst, int64_t n, char* stage,
+                           size_t cap) {
+  if (s->precision == BGK_FP64) {
+    HIP_TRY(hipMemcpyAsync(dst, h, (size_t)n * 8, hipMemcpyHostToDevice, s->stream));
+    return BGK_OK;
+  }
+  const int64_t per = (int64_t)(cap / 8);
+  for (int64_t o = 0; o < n; o += per) {
+    const int64_t m = std::min(per, n - o);
+    HIP_TRY(hipMemcpyAsync(stage, h + o, (size_t)m * 8, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_to_storage(s->precision, (const double*)stage, (char*)dst + o * s->s_bytes(), m,
+                              s->stream));
+  }
+  return BGK_OK;
+}
+
+bgk_status storage_to_host(bgk_solver* s, const void* src, double* h, int64_t n, char* stage,
+                           size_t cap) {
+  if (s->precision == BGK_FP64) {
+    HIP_TRY(hipMemcpyAsync(h, src, (size_t)n * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return BGK_OK;
+  }
+  const int64_t per = (int64_t)(cap / 8);
+  for (int64_t o = 0; o < n; o += per) {
+    const int64_t m = std::min(per, n - o);
+    HIP_TRY(launch_from_storage(s->precision, (const char*)src + o * s->s_bytes(), (double*)stage,
+                                m, s->stream));
+    HIP_TRY(hipMemcpyAsync(h + o, stage, (size_t)m * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return BGK_OK;
+}
+
+// Record the next timing event on the stream (timing mode only).
+bgk_status mark(bgk_solver* s) {
+  if (!s->timing) return BGK_OK;
+  if (s->used == s->pool.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    s->pool.push_back(e);
+  }
+  HIP_TRY(hipEventRecord(s->pool[s->used++], s->stream));
+  return BGK_OK;
+}
+
+bgk_status reset_state_flags(bgk_solver* s) {
+  HIP_TRY(hipMemsetAsync(s->diag(), 0, 8 * sizeof(unsigned long long), s->stream));
+  s->counters_ready = true;
+  s->failed = false;
+  s->has_state = true;
+  s->partials_valid = false;
+  return BGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bgk_status_str(bgk_status st) {
+  switch (st) {
+    case BGK_OK: return "BGK_OK";
+    case BGK_ERR_INVALID_ARG: return "BGK_ERR_INVALID_ARG";
+    case BGK_ERR_UNSUPPORTED: return "BGK_ERR_UNSUPPORTED";
+    case BGK_ERR_OUT_OF_MEMORY: return "BGK_ERR_OUT_OF_MEMORY";
+    case BGK_ERR_DEVICE: return "BGK_ERR_DEVICE";
+    case BGK_ERR_NEWTON: return "BGK_ERR_NEWTON";
+    case BGK_ERR_NONFINITE: return "BGK_ERR_NONFINITE";
+    case BGK_ERR_STATE: return "BGK_ERR_STATE";
+  }
+  return "BGK_UNKNOWN";
+}
+
+const char* bgk_last_error(void) { return g_last_error.c_str(); }
+
+bgk_status bgk_query_footprint(const bgk_problem* pb, size_t* bytes, int64_t* nx, int64_t* nv) {
+  bgk_status st = validate(pb);
+  if (st) return st;
+  Layout L = layout_of(pb);
+  if ((double)L.nchunk * (double)L.ne >= 4294967295.0 || (double)L.nx * L.nchunk >= 2147483647.0)
+    return fail(BGK_ERR_UNSUPPORTED, "problem too large for one launch grid");
+  if (bytes) *bytes = L.total;
+  if (nx) *nx = L.nx;
+  if (nv) *nv = L.nv;
+  return BGK_OK;
+}
+
+bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* stream,
+                      bgk_solver** out) {
+  if (!out) return fail(BGK_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  bgk_status st = bgk_query_footprint(pb, &need, nullptr, nullptr);
+  if (st) return st;
+  if (!ws) return fail(BGK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws) % kAlign) return fail(BGK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (bytes < need)
+    return fail(BGK_ERR_OUT_OF_MEMORY, "workspace %zu bytes < footprint %zu", bytes, need);
+  bgk_solver* s = new (std::nothrow) bgk_solver();
+  if (!s) return fail(BGK_ERR_OUT_OF_MEMORY, "host allocation failed");
+  s->pb = *pb;
+  s->L = layout_of(pb);
+  s->ws = (char*)ws;
+  s->stream = (hipStream_t)stream;
+  s->precision = pb->precision;
+  s->gamma = pb->gamma > 0.0 ? pb->gamma : 5.0 / 3.0;
+  DevGeom& g = s->g;
+  memset(&g, 0, sizeof(g));
+  g.dim = pb->dim;
+  g.n1 = pb->order + 1;
+  g.ns = s->L.ns;
+  for (int k = 0; k < 3; ++k) {
+    g.nelem[k] = k < pb->dim ? pb->nelem[k] : 1;
+    g.bc[k][0] = k < pb->dim ? pb->bc[k][0] : 0;
+    g.bc[k][1] = k < pb->dim ? pb->bc[k][1] : 0;
+    g.scale[k] = k < pb->dim ? 2.0 / ((pb->xhi[k] - pb->xlo[k]) / pb->nelem[k]) : 0.0;
+    g.nv1[k] = pb->nvel[k];
+    g.vlo[k] = pb->vlo[k];
+    g.du[k] = (pb->vhi[k] - pb->vlo[k]) / (pb->nvel[k] - 1);
+  }
+  g.ne = s->L.ne;
+  g.nx = s->L.nx;
+  g.nv = s->L.nv;
+  g.nchunk = s->L.nchunk;
+  build_ops(g.n1, g.dim, s->op);
+  *out = s;
+  return BGK_OK;
+}
+
+bgk_status bgk_destroy(bgk_solver* s) {
+  if (s)
+    for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
+  delete s;
+  return BGK_OK;
+}
+
+bgk_status bgk_node_coords(const bgk_solver* s, double* x) {
+  if (!s || !x) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  double xi[kMaxN1];
+  gauss_nodes(s->g.n1, xi);
+  const int d = s->g.dim, n1 = s->g.n1, ns = s->g.ns;
+  for (int64_t e = 0; e < s->g.ne; ++e) {
+    int64_t r = e;
+    int ek[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) {
+      ek[k] = (int)(r % s->g.nelem[k]);
+      r /= s->g.nelem[k];
+    }
+    for (int i = 0; i < ns; ++i) {
+      int q = i;
+      for (int k = 0; k < d; ++k) {
+        const int a = q % n1;
+        q /= n1;
+        const double h = (s->pb.xhi[k] - s->pb.xlo[k]) / s->pb.nelem[k];
+        x[(e * ns + i) * d + k] = s->pb.xlo[k] + h * (ek[k] + 0.5 * (1.0 + xi[a]));
+      }
+    }
+  }
+  return BGK_OK;
+}
+
+bgk_status bgk_velocity_grid(const bgk_solver* s, double* u, double* w) {
+  if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
+  const DevGeom& g = s->g;
+  for (int64_t j = 0; j < g.nv; ++j) {
+    const int b[3] = {(int)(j % g.nv1[0]), (int)((j / g.nv1[0]) % g.nv1[1]),
+                      (int)(j / ((int64_t)g.nv1[0] * g.nv1[1]))};
+    double wj = 1.0;
+    for (int c = 0; c < 3; ++c) {
+      if (u) u[3 * j + c] = g.vlo[c] + b[c] * g.du[c];
+      double wc = g.du[c];
+      if (b[c] == 0 || b[c] == g.nv1[c] - 1) wc *= 0.5;
+      wj *= wc;
+    }
+    if (w) w[j] = wj;
+  }
+  return BGK_OK;
+}
+
+bgk_status bgk_set_state(bgk_solver* s, const double* f, int32_t where) {
+  if (!s || !f) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
+  const int64_t n = s->L.nx * s->L.nv;
+  if (where == BGK_DEVICE) {
+    HIP_TRY(launch_to_storage(s->precision, f, s->f(0), n, s->stream));
+  } else {
+    bgk_status st = host_to_storage(s, f, s->f(0), n, (char*)s->f(1), 2 * s->L.fbytes);
+    if (st) return st;
+  }
+  return reset_state_flags(s);
+}
+
+bgk_status bgk_set_maxwellian(bgk_solver* s, const double* prim, int32_t where) {
+  if (!s || !prim) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
+  const double* dprim = prim;
+  if (where == BGK_HOST) {
+    for (int64_t i = 0; i < s->L.nx; ++i)
+      if (!(prim[5 * i] > 0.0) || !(prim[5 * i + 4] > 0.0))
+        return fail(BGK_ERR_INVALID_ARG, "node %lld: rho and theta must be > 0", (long long)i);
+    HIP_TRY(hipMemcpyAsync(s->prim(), prim, (size_t)s->L.nx * 5 * 8, hipMemcpyHostToDevice,
+                           s->stream));
+    dprim = s->prim();
+  }
+  HIP_TRY(launch_maxwellian(s->precision, s->g, dprim, s->f(0), s->stream));
+  bgk_status st = reset_state_flags(s);
+  if (where == BGK_HOST) HIP_TRY(hipStreamSynchronize(s->stream));
+  return st;
+}
+
+bgk_status bgk_get_state(bgk_solver* s, double* f, int32_t where) {
+  if (!s || !f) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+  if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
+  const int64_t n = s->L.nx * s->L.nv;
+  if (where == BGK_DEVICE) {
+    HIP_TRY(launch_from_storage(s->precision, s->f(0), f, n, s->stream));
+  } else {
+    bgk_status st = storage_to_host(s, s->f(0), f, n, (char*)s->f(1), 2 * s->L.fbytes);
+    if (st) return st;
+  }
+  return check_failed(s);
+}
+
+bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_t where) {
+  if (!s || !r_out) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
+  if (s->failed) return fail(BGK_ERR_STATE, "solver failed earlier; install a new state");
+  if (!f_in && !s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+  {
+    bgk_status st = ensure_counters(s);
+    if (st) return st;
+  }
+  const int64_t n = s->L.nx * s->L.nv;
+  const void* fin = s->f(0);
+  if (f_in) {
+    if (where == BGK_DEVICE) {
+      HIP_TRY(launch_to_storage(s->precision, f_in, s->f(1), n, s->stream));
+    } else {
+      // FP64: f1 holds the input directly; FP32: stage through f2
+      bgk_status st = host_to_storage(s, f_in, s->f(1), n, (char*)s->f(2), s->L.fbytes);
+      if (st) return st;
+    }
+    fin = s->f(1);
+    bgk_status st = moments_of(s, fin);
+    if (st) return st;
+    s->partials_valid = false;  // the partials now belong to f_in
+  } else {
+    bgk_status st = ensure_partials(s);
+    if (st) return st;
+  }
+  NewtonArgs N = newton_args(s);
+  HIP_TRY(launch_newton(N, s->stream));
+  StageArgs A = stage_args(s);
+  A.fin = fin;
+  if (where == BGK_DEVICE) {
+    A.out = r_out;
+    HIP_TRY(launch_stage(s->precision, 1, A, s->stream));
+    return BGK_OK;
+  }
+  // host output: element ranges that fit the f2 region as FP64
+  const size_t per_elem = (size_t)s->L.ns * s->L.nv * 8;
+  const int64_t cap = (int64_t)(s->L.fbytes / per_elem);
+  if (cap < 1)
+    return fail(BGK_ERR_UNSUPPORTED, "host residual with FP32 storage needs >= 2 elements; "
+                "use device buffers");
+  for (int64_t e0 = 0; e0 < s->L.ne; e0 += cap) {
+    A.e0 = e0;
+    A.ecount = std::min(cap, s->L.ne - e0);
+    A.out_e0 = e0;
+    A.out = s->f(2);
+    HIP_TRY(launch_stage(s->precision, 1, A, s->stream));
+    HIP_TRY(hipMemcpyAsync(r_out + e0 * s->L.ns * s->L.nv, s->f(2), (size_t)A.ecount * per_elem,
+                           hipMemcpyDeviceToHost, s->stream));
+  }
+  return check_failed(s);
+}
+
+bgk_status bgk_rk3_step(bgk_solver* s, double dt, int32_t nsteps) {
+  if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(BGK_ERR_INVALID_ARG, "dt must be > 0");
+  if (nsteps < 0) return fail(BGK_ERR_INVALID_ARG, "nsteps < 0");
+  if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+  if (s->failed) return fail(BGK_ERR_STATE, "solver failed earlier; install a new state");
+  bgk_status st = ensure_partials(s);
+  if (st) return st;
+  static const double kA[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double kB[3] = {1.0, 0.25, 2.0 / 3.0};
+  NewtonArgs N = newton_args(s);
+  N.Q = nullptr;
+  StageArgs A = stage_args(s);
+  A.dt = dt;
+  A.fn = s->f(0);
+  if (s->timing) {
+    if (s->used > 0) s->kinds.push_back(2);  // host gap between calls: not a kernel
+    if ((st = mark(s))) return st;
+  }
+  for (int32_t step = 0; step < nsteps; ++step) {
+    for (int k = 0; k < 3; ++k) {
+      HIP_TRY(launch_newton(N, s->stream));
+      if (s->timing) {
+        s->kinds.push_back(0);
+        if ((st = mark(s))) return st;
+      }
+      A.fin = s->f(k);
+      A.out = s->f((k + 1) % 3);
+      A.a = kA[k];
+      A.b = kB[k];
+      HIP_TRY(launch_stage(s->precision, 0, A, s->stream));
+      if (s->timing) {
+        s->kinds.push_back(1);
+        if ((st = mark(s))) return st;
+      }
+    }
+  }
+  return BGK_OK;
+}
+
+bgk_status bgk_timing_enable(bgk_solver* s, int32_t on) {
+  if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
+  if (!on && s->timing) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->used = 0;
+    s->kinds.clear();
+  }
+  s->timing = on != 0;
+  return BGK_OK;
+}
+
+bgk_status bgk_timing_read(bgk_solver* s, bgk_timing* out) {
+  if (!s || !out) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  memset(out, 0, sizeof(*out));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (size_t i = 0; i < s->kinds.size() && i + 1 < s->used; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->pool[i], s->pool[i + 1]));
+    if (s->kinds[i] == 1) {
+      out->stage_launches += 1;
+      out->stage_ms += ms;
+    } else if (s->kinds[i] == 0) {
+      out->newton_launches += 1;
+      out->newton_ms += ms;
+    }
+  }
+  s->used = 0;
+  s->kinds.clear();
+  return BGK_OK;
+}
+
+bgk_status bgk_moments(bgk_solver* s, double* Q, int32_t where) {
+  if (!s || !Q) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+  if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
+  bgk_status st = ensure_partials(s);
+  if (st) return st;
+  double* dst = where == BGK_DEVICE ? Q : s->Q();
+  HIP_TRY(launch_reduce_partials(s->g, s->partials(), dst, s->stream));
+  if (where == BGK_HOST)
+    HIP_TRY(hipMemcpyAsync(Q, s->Q(), (size_t)s->L.nx * 5 * 8, hipMemcpyDeviceToHost, s->stream));
+  return check_failed(s);
+}
+
+bgk_status bgk_stable_dt(bgk_solver* s, double cfl, double* dt) {
+  if (!s || !dt) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (!(cfl > 0.0)) return fail(BGK_ERR_INVALID_ARG, "cfl must be > 0");
+  const DevGeom& g = s->g;
+  double smax = 0.0;
+  for (int bz = 0; bz < g.nv1[2]; ++bz)
+    for (int by = 0; by < g.nv1[1]; ++by)
+      for (int bx = 0; bx < g.nv1[0]; ++bx) {
+        const int b[3] = {bx, by, bz};
+        double sum = 0.0;
+        for (int k = 0; k < g.dim; ++k) sum += fabs(g.vlo[k] + b[k] * g.du[k]) * (0.5 * g.scale[k]);
+        smax = std::max(smax, sum);
+      }
+  double out = cfl / smax;
+  if (s->pb.mu_ref > 0.0) {
+    if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+    double* Qh = new (std::nothrow) double[(size_t)s->L.nx * 5];
+    if (!Qh) return fail(BGK_ERR_OUT_OF_MEMORY, "host allocation failed");
+    bgk_status st = bgk_moments(s, Qh, BGK_HOST);
+    if (st) {
+      delete[] Qh;
+      return st;
+    }
+    double tmin = INFINITY;
+    for (int64_t i = 0; i < s->L.nx; ++i) {
+      const double* q = Qh + 5 * i;
+      const double rho = q[0];
+      const double UU = (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / (rho * rho);
+      const double P = (s->gamma - 1.0) * (q[4] - 0.5 * rho * UU);
+      const double th = P / rho;
+      const double tau = s->pb.mu_ref * pow(th / s->pb.theta_ref, s->pb.omega) / P;
+      tmin = std::min(tmin, tau);
+    }
+    delete[] Qh;
+    out = std::min(out, tmin);
+  }
+  *dt = out;
+  return BGK_OK;
+}
+
+bgk_status bgk_diagnostics(bgk_solver* s, bgk_diag* out) {
+  if (!s || !out) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  unsigned long long d[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (s->counters_ready) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(d, s->diag(), sizeof(d), hipMemcpyDeviceToHost));
+  }
+  out->newton_it_max = (int64_t)d[0];
+  out->newton_fail = (int64_t)d[1];
+  out->limiter_hits = (int64_t)d[2];
+  out->limiter_bad = (int64_t)d[3];
+  out->stages = (int64_t)d[4];
+  if (d[1] > 0) {
+    s->failed = true;
+    return fail(BGK_ERR_NEWTON, "%llu node solve(s) failed", d[1]);
+  }
+  return BGK_OK;
+}
+
+bgk_status bgk_synchronize(bgk_solver* s) {
+  if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
+  return check_failed(s);
+}
+
+}  // extern "C"

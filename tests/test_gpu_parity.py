@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Tolerances (FP64 storage):
+  * states (set, after RK3 steps): max |f_gpu - f_orc| <= 1e-12 max |f_orc|;
+  * residual L = -T + C: max |L_gpu - L_orc| <= 1e-12 (max|T_orc| + max|C_orc|),
+    i.e. relative to the size of the two terms whose difference L is (the
+    collision term alone is amplified by 1/tau, so a bare relative error of L
+    would measure cancellation, not the kernel);
+  * moments: <= 1e-13 relative to rho (mass, momentum) and E (energy).
+Every case prints its name, shape and seed before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2308_06196_amd import workloads as wl
+from tests.helpers import field_errors, initial_state, oracle_problem, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible GPU"
+    return t
+
+
+def solver(pb, precision=0):
+    from paper_2308_06196_amd import bgk
+    return bgk.Solver(pb, precision=precision)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+# Small cases covering every (d, p), periodic and specular, ragged velocity
+# counts (N_v below, between and above multiples of the 256-wide chunk).
+CASES = {
+    "d1p1_sod_spec": (wl.sod1d(nelem=6, order=1, nv1=8), "sod1d"),
+    "d1p2_sod_spec": (wl.sod1d(nelem=5, order=2, nv1=10), "sod1d"),
+    "d1p3_sod_spec": (wl.sod1d(nelem=4, order=3, nv1=6), "sod1d"),
+    "d2p1_box": (wl.box2d(n=3, order=1, nv1=7), "box2d"),
+    "d2p2_box": (wl.box2d(n=3, order=2, nv1=8), "box2d"),
+    "d2p3_box": (wl.box2d(n=2, order=3, nv1=9), "box2d"),
+    "d3p1_tgv": (wl.tgv3d(n=2, order=1, nv1=6), "tgv3d"),
+    "d3p2_tgv": (wl.tgv3d(n=2, order=2, nv1=5), "tgv3d"),
+    "d3p3_tgv": (wl.tgv3d(n=2, order=3, nv1=4), "tgv3d"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_maxwellian_and_state_roundtrip(torch, name):
+    pb, kind = CASES[name]
+    _say("maxwellian", name, pb["nelem"], pb["order"], pb["nvel"])
+    pr = oracle_problem(pb)
+    s = solver(pb)
+    x = s.node_coords()
+    prim = wl.PRIM[kind](x)
+    s.set_maxwellian(prim)
+    f_gpu = s.get_state().cpu().numpy()
+    f_orc = orc.maxwellian(pr, wl.PRIM[kind](orc.node_coords(pr)))
+    assert rel_max(f_gpu, f_orc) < 1e-13
+    # exact round trip of an arbitrary FP64 state, host and device paths
+    g = initial_state(pb, kind, seed=1, amp=0.3)
+    s.set_state(dev(torch, g))
+    assert np.array_equal(s.get_state().cpu().numpy(), g)
+    s.set_state(g)
+    out = np.zeros_like(g)
+    s.get_state(out)
+    assert np.array_equal(out, g)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_moments_match_oracle(torch, name):
+    pb, kind = CASES[name]
+    _say("moments", name)
+    f = initial_state(pb, kind, seed=2, amp=0.3)
+    s = solver(pb)
+    s.set_state(dev(torch, f))
+    Q = s.moments().cpu().numpy()
+    Qo = orc.moments(oracle_problem(pb), f)
+    scale = np.column_stack([Qo[:, 0]] * 4 + [Qo[:, 4]])
+    assert np.abs(Q - Qo).max() / 1.0 < 1e-13 * scale.max()
+    assert (np.abs(Q - Qo) / scale).max() < 1e-13
+
+
+def _residual_case(torch, pb, kind, seed, precision=0):
+    pr = oracle_problem(pb)
+    f = initial_state(pb, kind, seed=seed, amp=0.3)
+    s = solver(pb, precision)
+    r = s.residual(dev(torch, f)).cpu().numpy()
+    T = orc.transport(pr, f)
+    Cc, dg = orc.collision(pr, f)
+    L, _ = orc.residual(pr, f)
+    scale = np.abs(T).max() + np.abs(Cc).max()
+    return float(np.abs(r - L).max() / scale), s
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_matches_oracle(torch, name):
+    pb, kind = CASES[name]
+    _say("residual", name)
+    err, s = _residual_case(torch, pb, kind, seed=3)
+    assert err < 1e-12, err
+    s.diagnostics()
+
+
+@pytest.mark.parametrize("name", ["d1p2_sod_spec", "d2p3_box", "d3p2_tgv"])
+def test_residual_anisotropic_velocity_grid(torch, name):
+    pb, kind = CASES[name]
+    pb = dict(pb)
+    n = pb["nvel"][0]
+    pb["nvel"] = [n, n + 3, n + 1]
+    pb["vlo"] = [-6.0, -5.0, -7.0] if pb["dim"] == 1 else [-6.0, -5.5, -7.0]
+    pb["vhi"] = [6.0, 5.0, 7.0] if pb["dim"] == 1 else [6.5, 5.0, 7.0]
+    if pb["dim"] > 1:
+        pb["bc"] = [(0, 0)] * 3
+    _say("residual-aniso", name, pb["nvel"])
+    err, _ = _residual_case(torch, pb, kind, seed=4)
+    assert err < 1e-12, err
+
+
+def test_residual_collisionless_and_installed_state(torch):
+    pb, kind = CASES["d2p2_box"]
+    pb = dict(pb, mu_ref=0.0)
+    _say("residual-nocoll")
+    f = initial_state(pb, kind, seed=5, amp=0.2)
+    s = solver(pb)
+    s.set_state(dev(torch, f))
+    r = s.residual().cpu().numpy()  # of the installed state
+    T = orc.transport(oracle_problem(pb), f)
+    assert rel_max(r, -T) < 1e-12
+
+
+def test_residual_host_buffers(torch):
+    pb, kind = CASES["d1p2_sod_spec"]
+    _say("residual-host")
+    f = initial_state(pb, kind, seed=6, amp=0.3)
+    pr = oracle_problem(pb)
+    L, _ = orc.residual(pr, f)
+    scale = np.abs(orc.transport(pr, f)).max() + np.abs(orc.collision(pr, f)[0]).max()
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        s = solver(pb, prec)
+        out = np.zeros_like(f)
+        s.residual(f, out)
+        assert np.abs(out - L).max() / scale < tol
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rk3_steps_match_oracle(torch, name):
+    pb, kind = CASES[name]
+    _say("rk3", name)
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, kind, seed=7, amp=0.2)
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb)
+    s.set_state(dev(torch, f0))
+    assert abs(s.stable_dt(0.1) - dt) <= 1e-14 * dt
+    s.rk3_step(dt, 3)
+    f_gpu = s.get_state().cpu().numpy()
+    f_orc, dg = orc.rk3_step(pr, f0, dt, 3)
+    assert rel_max(f_gpu, f_orc) < 1e-12
+    d = s.diagnostics()
+    assert d["newton_fail"] == 0 and d["stages"] == 9
+
+
+def test_sod_full_run_fp64(torch):
+    """Shock tube, 32 elements p=2, 16^3 on [-6,6]^3, Kn=1e-2, specular walls,
+    CFL 0.1, 100 SSP-RK3 steps, FP64, limiter on."""
+    pb = wl.sod1d()
+    _say("sod-full", pb["nelem"], pb["nvel"])
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "sod1d")
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb)
+    s.set_state(dev(torch, f0))
+    s.rk3_step(dt, 100)
+    f_gpu = s.get_state().cpu().numpy()
+    f_orc, dg = orc.rk3_step(pr, f0, dt, 100)
+    assert rel_max(f_gpu, f_orc) < 1e-12
+    errs = field_errors(pb, s.moments().cpu().numpy(), orc.moments(pr, f_orc))
+    assert max(errs.values()) < 1e-12, errs
+    d = s.diagnostics()
+    assert d["limiter_hits"] == dg["limiter_hits"]
+
+
+def test_box2d_reduced_fp64_and_conservation(torch):
+    """2-D periodic box (C2's IC and velocity grid) on 4x4 elements, p=3, 20 steps."""
+    pb = wl.box2d(n=4)
+    _say("box2d-reduced", pb["nelem"], pb["nvel"])
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "box2d")
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb)
+    s.set_state(dev(torch, f0))
+    W = _node_weights(pb)
+    tot0 = W @ s.moments().cpu().numpy()
+    s.rk3_step(dt, 20)
+    tot1 = W @ s.moments().cpu().numpy()
+    f_gpu = s.get_state().cpu().numpy()
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 20)
+    assert rel_max(f_gpu, f_orc) < 1e-12
+    scale = np.array([tot0[0]] * 4 + [tot0[4]])
+    assert (np.abs(tot1 - tot0) / scale).max() < 1e-13 * 20
+
+
+def _node_weights(pb):
+    _, wq = orc.gauss_legendre(pb["order"] + 1)
+    W = wq
+    for _ in range(pb["dim"] - 1):
+        W = np.outer(W, wq).ravel()
+    ne = int(np.prod(pb["nelem"][: pb["dim"]]))
+    return np.tile(W, ne)
+
+
+def test_fp32_bulk_fields_within_tolerance(torch):
+    """FP32 storage and transport, FP64 moments/Newton: per-field error after 20 steps."""
+    pb = wl.box2d(n=4)
+    _say("box2d-fp32", pb["nelem"])
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "box2d")
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb, precision=1)
+    s.set_state(dev(torch, f0))
+    s.rk3_step(dt, 20)
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 20)
+    errs = field_errors(pb, s.moments().cpu().numpy(), orc.moments(pr, f_orc))
+    print("fp32 field errors", errs)
+    assert max(errs.values()) < 1e-5, errs
+    assert rel_max(s.get_state().cpu().numpy(), f_orc) < 1e-5
+
+
+def test_numerical_failure_is_reported(torch):
+    from paper_2308_06196_amd import bgk
+    pb, kind = CASES["d1p1_sod_spec"]
+    _say("failure-path")
+    s = solver(pb)
+    with pytest.raises(bgk.BGKError) as ei:
+        s.set_maxwellian(np.tile([-1.0, 0, 0, 0, 1.0], (s.nx, 1)))
+    assert ei.value.status == 1
+    f = initial_state(pb, kind)
+    f[0, 0, :] *= -1.0  # one node with negative density: not realizable
+    s.set_state(dev(torch, f))
+    s.rk3_step(1e-4, 1)
+    with pytest.raises(bgk.BGKError) as ei:
+        s.synchronize()
+    assert ei.value.status == 5
+    with pytest.raises(bgk.BGKError) as ei:
+        s.rk3_step(1e-4, 1)
+    assert ei.value.status == 7
+    s.set_state(dev(torch, initial_state(pb, kind)))  # recovers
+    s.rk3_step(1e-4, 1)
+    s.synchronize()
