@@ -6,15 +6,20 @@
 //                        of nv values per spatial node)
 //   partials[node][chunk][5]  FP64 moment partial sums of one stage output,
 //                        one entry per 256-wide velocity chunk
-//   params[node][8]      FP64 (alpha_0..alpha_4, 1/tau, tau, flag) of the
+//   params[node][8]      FP64 (alpha_0..alpha_4, 1/tau, tau, status) of the
 //                        discretely conservative equilibrium
+//   etab[node][S]        FP64 one-dimensional factors of that equilibrium,
+//                        S = nv1[0] + nv1[1] + nv1[2]:
+//                        g(u) = Ex[bx] Ey[by] Ez[bz] with
+//                        Ex[b] = exp(alpha_0 + alpha_1 u_b + alpha_4 u_b^2/2),
+//                        Ey[b] = exp(alpha_2 u_b + alpha_4 u_b^2/2), Ez alike
 //
 // Thread mapping of the stage kernel: one work-group = one element x one
-// chunk of 256 consecutive velocities; one thread = one velocity j and all
+// chunk of 256 consecutive velocities; one lane = one velocity j and all
 // (p+1)^d nodes of the element, held in registers. The FR operators are
 // (p+1)-point contractions along element lines (sum factorisation, VALU);
 // they are far below the FP64/FP32 ridge point, so the kernel is bound by
-// HBM traffic, not by arithmetic.
+// HBM traffic and instruction issue, not by arithmetic peak.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,16 +27,18 @@
 
 namespace bgk {
 
-constexpr int kMaxN1 = 4;      // p <= 3
-constexpr int kMaxNS = 64;     // (p+1)^d <= 64
-constexpr int kBlock = 256;    // velocities per work-group
-constexpr int kNumXCD = 8;     // MI355X: 8 accelerator complex dies
+constexpr int kMaxN1 = 4;            // p <= 3
+constexpr int kMaxNS = 64;           // (p+1)^d <= 64
+constexpr int kBlock = 256;          // velocities per work-group
+constexpr int kNumXCD = 8;           // MI355X: 8 accelerator complex dies
+constexpr int kMaxTabBytes = 65536;  // LDS for one element's equilibrium factors
 
 struct DevGeom {
   int32_t dim, n1, ns;
   int32_t nelem[3];
   int32_t bc[3][2];
   int32_t nv1[3];
+  int32_t tabw;  // S = nv1[0] + nv1[1] + nv1[2]
   int64_t ne, nx, nv;
   int32_t nchunk;
   double vlo[3], du[3];
@@ -49,12 +56,13 @@ struct DevOps {
 struct StageArgs {
   DevGeom g;
   DevOps op;
-  const void* fin;   // stage input (storage precision)
-  const void* fn;    // f^n (storage precision), read when a != 0
-  void* out;         // stage output (storage precision), or FP64 residual
+  const void* fin;  // stage input (storage precision)
+  const void* fn;   // f^n (storage precision), read when a != 0
+  void* out;        // stage output (storage precision), or FP64 residual
   const double* params;
+  const double* etab;
   double* partials;
-  unsigned long long* diag;  // [0] newton it max, [1] newton fail, [2] lim hits, [3] lim bad
+  unsigned long long* diag;  // newton it max, newton fail, lim hits, lim bad, stages
   double dt, a, b;
   int64_t e0, ecount, out_e0;
   int32_t limiter, collide;
@@ -64,6 +72,7 @@ struct NewtonArgs {
   DevGeom g;
   const double* partials;
   double* params;
+  double* etab;
   double* Q;  // optional [nx][5] output of the reduced moments
   unsigned long long* diag;
   double gamma, mu_ref, theta_ref, omega, tol;
@@ -82,21 +91,34 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
 }
 
 // ---------------------------------------------------------------------------
-// Work-group reduction of M per-lane FP64 values (fixed order, no atomics).
-// Butterfly reduce-scatter across the 64 lanes while the count is even,
-// all-reduce for the remaining lane bits, then a sum over the 4 waves in LDS.
+// Work-group reduction of per-lane FP64 values (fixed order, no atomics).
+//
+// A butterfly reduce-scatter over the 64 lanes: at the level of lane bit o,
+// lanes with the bit clear keep the lower half of their values and lanes
+// with it set keep the upper half, each adding the partner's copy of the
+// kept half. Partners: bits 5 and 4 via gfx950's v_permlane32_swap /
+// v_permlane16_swap (swap the odd 32-/16-lane rows of the first operand
+// with the even rows of the second, which needs no select); bit 3 via DPP
+// row_ror:8 (lane ^ 8 inside a 16-lane row); bit 2 via row_half_mirror
+// (lane -> 7 - lane inside 8 lanes, which pairs the two halves); bits 1 and
+// 0 via quad_perm. Odd counts are all-reduced on that bit instead.
 // ---------------------------------------------------------------------------
 constexpr int shuffle_cost(int m) {
   int c = 0;
   for (int o = 32; o >= 1; o >>= 1) {
-    if ((m & 1) == 0) { m >>= 1; c += m; } else { c += m; }
+    if ((m & 1) == 0) {
+      m >>= 1;
+      c += m;
+    } else {
+      c += m;
+    }
   }
   return c;
 }
-// nodes per reduction group: the largest divisor of NS not above 9
+// nodes per reduction group: the largest divisor of NS not above 8
 constexpr int group_of(int ns) {
   int g = 1;
-  for (int d = 1; d <= 9 && d <= ns; ++d)
+  for (int d = 1; d <= 8 && d <= ns; ++d)
     if (ns % d == 0) g = d;
   return g;
 }
@@ -104,15 +126,14 @@ constexpr int best_pad(int m) {
   int best = m, bc = shuffle_cost(m);
   for (int k = 1; k <= 64; k <<= 1) {
     int mp = (m + k - 1) / k * k;
-    if (shuffle_cost(mp) < bc) { bc = shuffle_cost(mp); best = mp; }
+    if (shuffle_cost(mp) < bc) {
+      bc = shuffle_cost(mp);
+      best = mp;
+    }
   }
   return best;
 }
 
-// Butterfly step across lane bit 32 (16): lanes with the bit clear return
-// x + x(partner), lanes with it set return y(partner) + y. gfx950's
-// v_permlane32_swap / v_permlane16_swap exchange the odd 32- (16-) lane rows
-// of the first operand with the even rows of the second.
 template <int O>
 __device__ __forceinline__ double swap_sum(double x, double y) {
   const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
@@ -128,11 +149,17 @@ __device__ __forceinline__ double swap_sum(double x, double y) {
   }
 }
 
-// One butterfly level per template instance (each level owns a fresh,
-// statically indexed array, which keeps every value in registers).
-// v[0..H) per lane at level STEP (lane bit 32 >> STEP is reduced next);
-// after the last level lds_wave[base + q] holds the wave total of index
-// base + q, written by the lanes whose all-reduced bits (dup) are zero.
+// Partner value across lane bit O (O <= 8) by a DPP move (all source lanes valid).
+template <int O>
+__device__ __forceinline__ double dpp_partner(double x) {
+  constexpr int ctrl = O == 8 ? 0x128 : O == 4 ? 0x141 : O == 2 ? 0x4E : 0xB1;
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One level per template instance (each level owns a fresh, statically
+// indexed array, which keeps every value in registers).
 template <int H, int STEP>
 __device__ __forceinline__ void wave_level(const double (&v)[H], double* lds_wave, int lane,
                                            int base, int dup) {
@@ -153,30 +180,31 @@ __device__ __forceinline__ void wave_level(const double (&v)[H], double* lds_wav
       } else {
 #pragma unroll
         for (int q = 0; q < HH; ++q) {
-          const double xs = v[q] + __shfl_xor(v[q], O, 64);
-          const double ys = v[q + HH] + __shfl_xor(v[q + HH], O, 64);
-          w[q] = up ? ys : xs;
+          const double send = up ? v[q] : v[q + HH];
+          const double keep = up ? v[q + HH] : v[q];
+          w[q] = keep + dpp_partner<O>(send);
         }
       }
       wave_level<HH, STEP + 1>(w, lds_wave, lane, base + (up ? HH : 0), dup);
     } else {
       double w[H];
+      if constexpr (O == 32) {
 #pragma unroll
-      for (int q = 0; q < H; ++q) w[q] = v[q] + __shfl_xor(v[q], O, 64);
+        for (int q = 0; q < H; ++q) w[q] = v[q] + __shfl_xor(v[q], 32, 64);
+      } else if constexpr (O == 16) {
+#pragma unroll
+        for (int q = 0; q < H; ++q) w[q] = v[q] + __shfl_xor(v[q], 16, 64);
+      } else {
+#pragma unroll
+        for (int q = 0; q < H; ++q) w[q] = v[q] + dpp_partner<O>(v[q]);
+      }
       wave_level<H, STEP + 1>(w, lds_wave, lane, base, dup | O);
     }
   }
 }
 
-// v[0..MP) per lane; on return lds_wave[idx] holds the wave total of idx.
-template <int MP>
-__device__ __forceinline__ void wave_reduce_to_lds(const double (&v)[MP], double* lds_wave,
-                                                   int lane) {
-  wave_level<MP, 0>(v, lds_wave, lane, 0, 0);
-}
-
 // ---------------------------------------------------------------------------
-// Per-thread velocity of velocity index j.
+// Per-lane velocity of velocity index j (32-bit index arithmetic).
 // ---------------------------------------------------------------------------
 struct Vel {
   int b[3];
@@ -184,11 +212,12 @@ struct Vel {
   double w;  // trapezoid weight
 };
 
-__device__ __forceinline__ Vel velocity_of(const DevGeom& g, int64_t j) {
+__device__ __forceinline__ Vel velocity_of(const DevGeom& g, int j) {
   Vel v;
-  v.b[0] = (int)(j % g.nv1[0]);
-  v.b[1] = (int)((j / g.nv1[0]) % g.nv1[1]);
-  v.b[2] = (int)(j / ((int64_t)g.nv1[0] * g.nv1[1]));
+  const int r = j / g.nv1[0];
+  v.b[0] = j - r * g.nv1[0];
+  v.b[2] = r / g.nv1[1];
+  v.b[1] = r - v.b[2] * g.nv1[1];
   double w = 1.0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -201,29 +230,46 @@ __device__ __forceinline__ Vel velocity_of(const DevGeom& g, int64_t j) {
   return v;
 }
 
+// Uniform kernel-argument value as an opaque scalar register value: a
+// per-lane select between two of them then stays a register select (the
+// compiler would otherwise turn it into a load through a selected address).
+__device__ __forceinline__ double sreg(double x) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int sreg(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 template <typename ST> struct Compute;
 template <> struct Compute<double> { using T = double; };
 template <> struct Compute<float> { using T = float; };
 
+// LDS doubles needed by the moment reduction of one element.
+template <int NS>
+constexpr int red_lds_doubles() {
+  return (kBlock / 64) * (NS / group_of(NS)) * best_pad(5 * group_of(NS));
+}
+
 // Moment partials of one element's NS node values (per lane), written for
 // this work-group's velocity chunk into partials[(node)*nchunk + chunk][5].
-// Values of lanes outside the grid must enter with w = 0.
+// Lanes outside the velocity grid must enter with w = 0. Contains one
+// work-group barrier.
 template <int NS, typename CT>
 __device__ __forceinline__ void element_partials(const CT (&fv)[NS], const Vel& vel,
                                                  double* __restrict__ partials, int64_t node0,
-                                                 int nchunk, int chunk, double* lds) {
-  // groups of nodes bound the register footprint of the reduction
+                                                 int nchunk, int chunk, double* red) {
   constexpr int G = group_of(NS);
+  constexpr int NG = NS / G;
   constexpr int M = 5 * G;
   constexpr int MP = best_pad(M);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
 #pragma unroll
-  for (int g0 = 0; g0 < NS; g0 += G) {
+  for (int gi = 0; gi < NG; ++gi) {
     double v[MP];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-      const double wf = vel.w * (double)fv[g0 + q];
+      const double wf = vel.w * (double)fv[gi * G + q];
       v[5 * q + 0] = wf;
       v[5 * q + 1] = wf * vel.u[0];
       v[5 * q + 2] = wf * vel.u[1];
@@ -232,15 +278,15 @@ __device__ __forceinline__ void element_partials(const CT (&fv)[NS], const Vel& 
     }
 #pragma unroll
     for (int q = M; q < MP; ++q) v[q] = 0.0;
-    wave_reduce_to_lds<MP>(v, lds + wave * MP, lane);
-    __syncthreads();
-    for (int t = threadIdx.x; t < M; t += blockDim.x) {
-      double s = lds[t];
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s += lds[w * MP + t];
-      const int q = t / 5, m = t % 5;
-      partials[((node0 + g0 + q) * nchunk + chunk) * 5 + m] = s;
-    }
-    __syncthreads();
+    wave_level<MP, 0>(v, red + (wave * NG + gi) * MP, lane, 0, 0);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
+    const int gi = t / M, idx = t - gi * M;
+    double s = red[gi * MP + idx];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) s += red[(w * NG + gi) * MP + idx];
+    partials[((node0 + t / 5) * nchunk + chunk) * 5 + (t % 5)] = s;
   }
 }
 
@@ -248,34 +294,33 @@ __device__ __forceinline__ void element_partials(const CT (&fv)[NS], const Vel& 
 // Stage kernel: FR transport (volume + upwind inflow-face lift) + BGK
 // relaxation + SSP-RK combine + positivity limiter + next-stage moment
 // partials (MODE 0), or the plain residual L(f) in FP64 (MODE 1).
+// Dynamic LDS: NS * S + NS values of type CT (equilibrium factors, 1/tau).
 // ---------------------------------------------------------------------------
 template <int DIM, int P, typename ST, int MODE>
 __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
-  __shared__ double lds[(kBlock / 64) * best_pad(5 * group_of(NS))];
+  // the upwind neighbours' nodes of every axis are loaded up front when they
+  // fit the register budget (1-D and 2-D elements); 3-D loads them per axis
+  constexpr bool kPreload = NS * DIM <= 48;
+  __shared__ double red[red_lds_doubles<NS>()];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = A.e0 + (w % A.ecount);
   const int64_t nv = g.nv;
-  const int64_t j = (int64_t)chunk * kBlock + threadIdx.x;
+  const int S = g.tabw;
+  const int64_t node0 = e * NS;
+
+  const int j = chunk * kBlock + (int)threadIdx.x;
   const bool valid = j < nv;
-  const int64_t jj = valid ? j : nv - 1;
+  const int jj = valid ? j : (int)nv - 1;
   Vel vel = velocity_of(g, jj);
   if (!valid) vel.w = 0.0;
-
-  const ST* __restrict__ fin = (const ST*)A.fin;
-  const ST* fe = fin + (e * NS) * nv + jj;
-  CT f[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
-
-  CT acc[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) acc[i] = (CT)0;
 
   // element coordinates (uniform over the work-group)
   int ek[3] = {0, 0, 0};
@@ -288,49 +333,134 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     }
   }
 
+  // Per axis: the upwind neighbour (left one when u_k > 0, right one
+  // otherwise) or, at a specular wall, the own element at the velocity with
+  // component k mirrored; the exterior trace is the neighbour's right trace
+  // (u_k > 0), its left trace (u_k < 0), or the own trace on the wall side.
+  const ST* __restrict__ fin = (const ST*)A.fin;
+  const ST* src[DIM];
+  bool pos[DIM], use_right[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    int S = 1;
-#pragma unroll
-    for (int m = 0; m < k; ++m) S *= N1;
-    const CT a = (CT)(vel.u[k] * g.scale[k]);
-    const bool pos = a > (CT)0;
-    // upwind neighbour along k: left one when a > 0, right one otherwise
-    const int side = pos ? 0 : 1;
-    int nk = ek[k] + (pos ? -1 : 1);
+    pos[k] = vel.u[k] * g.scale[k] > 0.0;
+    const int nek = sreg(g.nelem[k]);
+    const bool wall_lo = sreg(g.bc[k][0]) != 0, wall_hi = sreg(g.bc[k][1]) != 0;
+    int nk = ek[k] + (pos[k] ? -1 : 1);
     bool wall = false;
-    if (nk < 0 || nk >= g.nelem[k]) {
-      if (g.bc[k][side] != 0) wall = true;
-      nk = (nk + g.nelem[k]) % g.nelem[k];
+    if (nk < 0 || nk >= nek) {
+      wall = pos[k] ? wall_lo : wall_hi;
+      nk = (nk + nek) % nek;
     }
     int64_t src_e = e;
-    int64_t src_j = jj;
+    int src_j = jj;
     if (wall) {
-      // specular wall: own element at the velocity with component k mirrored
       int bm[3] = {vel.b[0], vel.b[1], vel.b[2]};
       bm[k] = g.nv1[k] - 1 - bm[k];
-      src_j = bm[0] + (int64_t)g.nv1[0] * (bm[1] + (int64_t)g.nv1[1] * bm[2]);
+      src_j = bm[0] + g.nv1[0] * (bm[1] + g.nv1[1] * bm[2]);
     } else {
       int64_t stride = 1;
       for (int m = 0; m < k; ++m) stride *= g.nelem[m];
       src_e = e + (int64_t)(nk - ek[k]) * stride;
     }
-    // exterior trace: right trace of the left neighbour (a > 0), left trace
-    // of the right neighbour (a < 0); at a wall the own trace on that side
-    const bool use_right = (pos != wall);
-    const ST* src = fin + (src_e * NS) * nv + src_j;
+    use_right[k] = (pos[k] != wall);
+    src[k] = fin + src_e * NS * nv + src_j;
+  }
+
+  // Issue the global loads before any use: the element's equilibrium
+  // factors and 1/tau (first batch), own nodes, f^n, the upwind neighbours'
+  // nodes.
+  constexpr int kU = 8;
+  const int ntab = NS * S;
+  const double* et = A.etab + node0 * S;
+  double tv[kU];
+  double itv = 0.0;
+  if (A.collide) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = u * kBlock + (int)threadIdx.x;
+      tv[u] = t < ntab ? et[t] : 0.0;
+    }
+    if (threadIdx.x < NS) itv = A.params[(node0 + threadIdx.x) * 8 + 5];
+  }
+  const ST* fe = fin + node0 * nv + jj;
+  CT f[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
+  CT fnv[NS];
+  if constexpr (MODE == 0) {
+    if (A.a != 0.0) {
+      const ST* fn = (const ST*)A.fn + node0 * nv + jj;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[(int64_t)i * nv];
+    }
+  }
+  CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
+  if constexpr (kPreload) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][(int64_t)i * nv];
+  }
+  // equilibrium factors (NS x S) and 1/tau (NS) of this element -> LDS
+  CT* itau = tab + NS * S;
+  if (A.collide) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = u * kBlock + (int)threadIdx.x;
+      if (t < ntab) tab[t] = (CT)tv[u];
+    }
+    if (threadIdx.x < NS) itau[threadIdx.x] = (CT)itv;
+    // factors beyond the first batch (large velocity grids or 3-D elements)
+    for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int t = t0 + u * kBlock + (int)threadIdx.x;
+        v[u] = t < ntab ? et[t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int t = t0 + u * kBlock + (int)threadIdx.x;
+        if (t < ntab) tab[t] = (CT)v[u];
+      }
+    }
+  }
+
+  CT acc[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) acc[i] = (CT)0;
+
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    int S1 = 1;
+#pragma unroll
+    for (int m = 0; m < k; ++m) S1 *= N1;
+    const CT a = (CT)(vel.u[k] * g.scale[k]);
+    CT lown[N1], lext[N1], Gin[N1];
+#pragma unroll
+    for (int bb = 0; bb < N1; ++bb) {
+      const CT lL = (CT)sreg(A.op.lamL[bb]), lR = (CT)sreg(A.op.lamR[bb]);
+      const CT gL = (CT)sreg(A.op.GL[bb]), gR = (CT)sreg(A.op.GR[bb]);
+      lown[bb] = pos[k] ? lL : lR;
+      lext[bb] = use_right[k] ? lR : lL;
+      Gin[bb] = pos[k] ? gL : gR;
+    }
 #pragma unroll
     for (int base = 0; base < NS; ++base) {
-      if ((base / S) % N1 != 0) continue;
+      if ((base / S1) % N1 != 0) continue;
       CT line[N1];
 #pragma unroll
-      for (int bb = 0; bb < N1; ++bb) line[bb] = f[base + bb * S];
+      for (int bb = 0; bb < N1; ++bb) line[bb] = f[base + bb * S1];
       CT own = (CT)0, ext = (CT)0;
 #pragma unroll
       for (int bb = 0; bb < N1; ++bb) {
-        const CT lL = (CT)A.op.lamL[bb], lR = (CT)A.op.lamR[bb];
-        own += (pos ? lL : lR) * line[bb];
-        ext += (use_right ? lR : lL) * (CT)src[(int64_t)(base + bb * S) * nv];
+        own += lown[bb] * line[bb];
+        CT xv;
+        if constexpr (kPreload)
+          xv = nbv[k][base + bb * S1];
+        else
+          xv = (CT)src[k][(int64_t)(base + bb * S1) * nv];
+        ext += lext[bb] * xv;
       }
       const CT jump = a * (ext - own);
 #pragma unroll
@@ -338,25 +468,23 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
         CT df = (CT)0;
 #pragma unroll
         for (int bb = 0; bb < N1; ++bb) df += (CT)A.op.D[ia][bb] * line[bb];
-        const CT G = pos ? (CT)A.op.GL[ia] : (CT)A.op.GR[ia];
-        acc[base + ia * S] += a * df + jump * G;
+        acc[base + ia * S1] += a * df + jump * Gin[ia];
       }
     }
   }
 
-  // BGK relaxation towards the discretely conservative equilibrium
-  // g = exp(alpha . psi) (FP64 argument and exponential)
-  const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
-  const int64_t node0 = e * NS;
+  // BGK relaxation towards the discretely conservative equilibrium,
+  // g = Ex[bx] Ey[by] Ez[bz] from the LDS factors
+  if (A.collide) __syncthreads();
+  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
   CT L[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     CT c = (CT)0;
     if (A.collide) {
-      const double* pr = A.params + (node0 + i) * 8;
-      const double arg = pr[0] + pr[1] * vel.u[0] + pr[2] * vel.u[1] + pr[3] * vel.u[2] + pr[4] * psi4;
-      const CT gq = (CT)exp(arg);
-      c = (gq - f[i]) * (CT)pr[5];
+      const CT* ti = tab + i * S;
+      const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
+      c = (gq - f[i]) * itau[i];
     }
     L[i] = -acc[i] + c;
   }
@@ -364,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   if constexpr (MODE == 1) {
     double* out = (double*)A.out;
     if (valid) {
-      double* oe = out + ((e - A.out_e0) * NS) * nv + j;
+      double* oe = out + (e - A.out_e0) * NS * nv + j;
 #pragma unroll
       for (int i = 0; i < NS; ++i) oe[(int64_t)i * nv] = (double)L[i];
     }
@@ -373,31 +501,30 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
     CT o[NS];
     if (A.a != 0.0) {
-      const ST* fn = (const ST*)A.fn + (e * NS) * nv + jj;
 #pragma unroll
-      for (int i = 0; i < NS; ++i) o[i] = ca * (CT)fn[(int64_t)i * nv] + cb * (f[i] + dt * L[i]);
+      for (int i = 0; i < NS; ++i) o[i] = ca * fnv[i] + cb * (f[i] + dt * L[i]);
     } else {
 #pragma unroll
       for (int i = 0; i < NS; ++i) o[i] = cb * (f[i] + dt * L[i]);
     }
     if (A.limiter) {
-      double mean = 0.0;
+      CT mean = (CT)0;
       CT fmin = o[0];
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        mean += A.op.W[i] * (double)o[i];
+        mean += (CT)A.op.W[i] * o[i];
         fmin = o[i] < fmin ? o[i] : fmin;
       }
-      mean /= A.op.Wsum;
+      mean /= (CT)A.op.Wsum;
       const bool hit = valid && (fmin < (CT)0);
-      if (hit && mean != (double)fmin) {
-        double beta = fabs(mean / (mean - (double)fmin));
-        beta = beta > 1.0 ? 1.0 : beta;
+      if (hit && mean != fmin) {
+        CT beta = fabs(mean / (mean - fmin));
+        beta = beta > (CT)1 ? (CT)1 : beta;
 #pragma unroll
-        for (int i = 0; i < NS; ++i) o[i] = (CT)(mean + beta * ((double)o[i] - mean));
+        for (int i = 0; i < NS; ++i) o[i] = mean + beta * (o[i] - mean);
       }
       const unsigned long long nh = __popcll(__ballot(hit));
-      const unsigned long long nb = __popcll(__ballot(hit && !(mean > 0.0)));
+      const unsigned long long nb = __popcll(__ballot(hit && !(mean > (CT)0)));
       if ((threadIdx.x & 63) == 0 && nh) {
         atomicAdd(&A.diag[2], nh);
         if (nb) atomicAdd(&A.diag[3], nb);
@@ -405,15 +532,12 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     }
     ST* out = (ST*)A.out;
     if (valid) {
-      ST* oe = out + (e * NS) * nv + j;
+      ST* oe = out + node0 * nv + j;
 #pragma unroll
       for (int i = 0; i < NS; ++i) oe[(int64_t)i * nv] = (ST)o[i];
     }
     // moment partials of what was stored (FP64 sums)
-    CT os[NS];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) os[i] = (CT)(ST)o[i];
-    element_partials<NS, CT>(os, vel, A.partials, node0, g.nchunk, chunk, lds);
+    element_partials<NS, CT>(o, vel, A.partials, node0, g.nchunk, chunk, red);
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
   }
 }
@@ -424,22 +548,22 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
-  __shared__ double lds[(kBlock / 64) * best_pad(5 * group_of(NS))];
+  __shared__ double red[red_lds_doubles<NS>()];
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = A.e0 + (w % A.ecount);
   const int64_t nv = g.nv;
-  const int64_t j = (int64_t)chunk * kBlock + threadIdx.x;
+  const int j = chunk * kBlock + (int)threadIdx.x;
   const bool valid = j < nv;
-  const int64_t jj = valid ? j : nv - 1;
+  const int jj = valid ? j : (int)nv - 1;
   Vel vel = velocity_of(g, jj);
   if (!valid) vel.w = 0.0;
-  const ST* fe = (const ST*)A.fin + (e * NS) * nv + jj;
+  const ST* fe = (const ST*)A.fin + e * NS * nv + jj;
   CT f[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
-  element_partials<NS, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, lds);
+  element_partials<NS, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, red);
 }
 
 }  // namespace bgk

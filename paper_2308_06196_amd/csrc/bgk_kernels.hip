@@ -58,23 +58,44 @@ __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
   return 0;
 }
 
+// All-reduce of one FP64 value over the 16 lanes of a team (fixed order;
+// every lane ends with the same bits).
+__device__ __forceinline__ double team_sum(double x) {
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) x += __shfl_xor(x, o, 16);
+  return x;
+}
+
+// One 16-lane team per spatial node. The lanes split the velocity chunks of
+// the moment partials and the nodes of each one-dimensional sum; the 5x5
+// solve is repeated identically in every lane of the team.
+constexpr int kTeam = 16;
+
 __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   const DevGeom& g = A.g;
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= g.nx) return;
+  const int64_t node_raw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kTeam;
+  const int r = threadIdx.x % kTeam;
+  // teams past the last node work on the last node and store nothing, so that
+  // every lane reaches the wave-level counter reduction at the end
+  const bool active = node_raw < g.nx;
+  const int64_t node = active ? node_raw : g.nx - 1;
   double Q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const double* pp = A.partials + node * g.nchunk * 5;
-  for (int c = 0; c < g.nchunk; ++c)
+  for (int c = r; c < g.nchunk; c += kTeam)
 #pragma unroll
     for (int m = 0; m < 5; ++m) Q[m] += pp[c * 5 + m];
-  if (A.Q) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Q[m] = team_sum(Q[m]);
+  if (A.Q && r == 0 && active) {
 #pragma unroll
     for (int m = 0; m < 5; ++m) A.Q[node * 5 + m] = Q[m];
   }
   double* out = A.params + node * 8;
-  if (!A.collide) {
+  if (!A.collide) {  // uniform over the grid
+    if (r == 0 && active) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) out[m] = 0.0;
+      for (int m = 0; m < 8; ++m) out[m] = 0.0;
+    }
     return;
   }
   const double rho = Q[0];
@@ -82,7 +103,7 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   const double P = (A.gamma - 1.0) * (Q[4] - 0.5 * rho * UU);
   const double th = P / rho;
   int status = 0, iters = 0;
-  double al[5];
+  double al[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (!(rho > 0.0) || !(th > 0.0)) {
     status = 2;
   } else {
@@ -100,7 +121,7 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
 #pragma unroll
         for (int n = 0; n < 5; ++n) S[c][n] = 0.0;
         const int N = g.nv1[c];
-        for (int b = 0; b < N; ++b) {
+        for (int b = r; b < N; b += kTeam) {
           const double u = g.vlo[c] + b * g.du[c];
           double wc = g.du[c];
           if (b == 0 || b == N - 1) wc *= 0.5;
@@ -112,6 +133,8 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
           S[c][3] += t * u2 * u;
           S[c][4] += t * u2 * u2;
         }
+#pragma unroll
+        for (int n = 0; n < 5; ++n) S[c][n] = team_sum(S[c][n]);
       }
       double m[3][5];
 #pragma unroll
@@ -144,15 +167,15 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
       J[4][4] = A0 * 0.25 *
                 (m[0][4] + m[1][4] + m[2][4] +
                  2.0 * (m[0][2] * m[1][2] + m[0][2] * m[2][2] + m[1][2] * m[2][2]));
-      double F[5], r = 0.0;
+      double F[5], res = 0.0;
 #pragma unroll
       for (int a = 0; a < 5; ++a) {
         F[a] = G[a] - Q[a];
         const double ra = fabs(F[a]) / sc[a];
-        if (!(ra <= r)) r = ra;
+        if (!(ra <= res)) res = ra;
       }
       iters = it + 1;
-      const bool conv = r <= A.tol;
+      const bool conv = res <= A.tol;
       if (!conv && it >= A.maxit) {
         status = 1;
         break;
@@ -184,16 +207,40 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   if (status) {
 #pragma unroll
     for (int a = 0; a < 5; ++a) al[a] = __builtin_nan("");
-    atomicAdd(&A.diag[1], 1ull);
   }
-  const double mu = A.mu_ref * pow(th / A.theta_ref, A.omega);
-  const double tau = mu / P;
+  // one-dimensional factors of the equilibrium, exp(alpha_0) folded into x
+  double* et = A.etab + node * g.tabw;
+  int off = 0;
 #pragma unroll
-  for (int a = 0; a < 5; ++a) out[a] = al[a];
-  out[5] = 1.0 / tau;
-  out[6] = tau;
-  out[7] = (double)status;
-  atomicMax(&A.diag[0], (unsigned long long)iters);
+  for (int c = 0; c < 3; ++c) {
+    const int N = g.nv1[c];
+    const double a0 = c == 0 ? al[0] : 0.0;
+    if (active) {
+      for (int b = r; b < N; b += kTeam) {
+        const double u = g.vlo[c] + b * g.du[c];
+        et[off + b] = exp(a0 + al[1 + c] * u + al[4] * (0.5 * u * u));
+      }
+    }
+    off += N;
+  }
+  if (r == 0 && active) {
+    const double mu = A.mu_ref * pow(th / A.theta_ref, A.omega);
+    const double tau = mu / P;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) out[a] = al[a];
+    out[5] = 1.0 / tau;
+    out[6] = tau;
+    out[7] = (double)status;
+  }
+  // counters: one atomic per wave (the four teams of a wave reduced first)
+  int itw = active ? iters : 0;
+  itw = max(itw, __shfl_xor(itw, 16, 64));
+  itw = max(itw, __shfl_xor(itw, 32, 64));
+  const unsigned long long nfail = __popcll(__ballot(active && r == 0 && status != 0));
+  if ((threadIdx.x & 63) == 0) {
+    if (itw > 0) atomicMax(&A.diag[0], (unsigned long long)itw);
+    if (nfail) atomicAdd(&A.diag[1], nfail);
+  }
 }
 
 // Q[node][5] from the partials (no Newton solve).
@@ -217,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_maxwellian(const DevGeom g, const do
   const int64_t w = blockIdx.x;
   const int64_t node = w / g.nchunk;
   const int chunk = (int)(w % g.nchunk);
-  const int64_t j = (int64_t)chunk * kBlock + threadIdx.x;
+  const int j = chunk * kBlock + (int)threadIdx.x;
   if (j >= g.nv) return;
   const Vel v = velocity_of(g, j);
   const double* q = prim + node * 5;
@@ -243,12 +290,13 @@ template <typename ST>
 static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   const dim3 grid((unsigned)(A.g.nchunk * A.ecount)), block(kBlock);
   const int key = A.g.dim * 10 + (A.g.n1 - 1);
+  const size_t lds = A.collide ? (size_t)A.g.ns * (A.g.tabw + 1) * sizeof(ST) : 0;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
     if (mode == 0)                                                         \
-      hipLaunchKernelGGL((k_stage<D, P, ST, 0>), grid, block, 0, s, A);    \
+      hipLaunchKernelGGL((k_stage<D, P, ST, 0>), grid, block, lds, s, A);  \
     else if (mode == 1)                                                    \
-      hipLaunchKernelGGL((k_stage<D, P, ST, 1>), grid, block, 0, s, A);    \
+      hipLaunchKernelGGL((k_stage<D, P, ST, 1>), grid, block, lds, s, A);  \
     else                                                                   \
       hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, 0, s, A);     \
     break;
@@ -269,7 +317,7 @@ hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t
 }
 
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_newton, dim3(grid_of(A.g.nx, 256)), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_newton, dim3(grid_of(A.g.nx * kTeam, 256)), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 

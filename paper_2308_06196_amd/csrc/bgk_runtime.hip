@@ -163,7 +163,7 @@ void gauss_nodes(int n1, double* xi) {
 }
 
 struct Layout {
-  size_t f[3], partials, params, Q, prim, diag, total;
+  size_t f[3], partials, params, etab, Q, prim, diag, total;
   int64_t nx, nv, ne;
   int ns, nchunk;
   size_t fbytes;
@@ -193,6 +193,16 @@ bgk_status validate(const bgk_problem* pb) {
     if (pb->nvel[c] < 2) return fail(BGK_ERR_INVALID_ARG, "nvel[%d] < 2", c);
     if (!(pb->vhi[c] > pb->vlo[c])) return fail(BGK_ERR_INVALID_ARG, "vhi[%d] <= vlo[%d]", c, c);
   }
+  {
+    int ns = 1;
+    for (int k = 0; k < pb->dim; ++k) ns *= pb->order + 1;
+    const double nv = (double)pb->nvel[0] * pb->nvel[1] * pb->nvel[2];
+    if (nv >= 2147483647.0) return fail(BGK_ERR_UNSUPPORTED, "velocity grid too large");
+    const size_t tab = (size_t)ns * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1) *
+                       (pb->precision == BGK_FP64 ? 8 : 4);
+    if (tab > (size_t)kMaxTabBytes)
+      return fail(BGK_ERR_UNSUPPORTED, "equilibrium factors of one element (%zu B) exceed LDS", tab);
+  }
   if (!(pb->theta_ref > 0.0) && pb->mu_ref > 0.0)
     return fail(BGK_ERR_INVALID_ARG, "theta_ref must be > 0");
   return BGK_OK;
@@ -218,6 +228,8 @@ Layout layout_of(const bgk_problem* pb) {
   off = align_up(off + (size_t)L.nx * L.nchunk * 5 * sizeof(double));
   L.params = off;
   off = align_up(off + (size_t)L.nx * 8 * sizeof(double));
+  L.etab = off;
+  off = align_up(off + (size_t)L.nx * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2]) * sizeof(double));
   L.Q = off;
   off = align_up(off + (size_t)L.nx * 5 * sizeof(double));
   L.prim = off;
@@ -252,6 +264,7 @@ struct bgk_solver {
   void* f(int b) const { return ws + L.f[b]; }
   double* partials() const { return (double*)(ws + L.partials); }
   double* params() const { return (double*)(ws + L.params); }
+  double* etab() const { return (double*)(ws + L.etab); }
   double* Q() const { return (double*)(ws + L.Q); }
   double* prim() const { return (double*)(ws + L.prim); }
   unsigned long long* diag() const { return (unsigned long long*)(ws + L.diag); }
@@ -266,6 +279,7 @@ StageArgs stage_args(const bgk_solver* s) {
   A.g = s->g;
   A.op = s->op;
   A.params = s->params();
+  A.etab = s->etab();
   A.partials = s->partials();
   A.diag = s->diag();
   A.e0 = 0;
@@ -282,6 +296,7 @@ NewtonArgs newton_args(const bgk_solver* s) {
   N.g = s->g;
   N.partials = s->partials();
   N.params = s->params();
+  N.etab = s->etab();
   N.Q = s->Q();
   N.diag = s->diag();
   N.gamma = s->gamma;
@@ -455,6 +470,7 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
     g.vlo[k] = pb->vlo[k];
     g.du[k] = (pb->vhi[k] - pb->vlo[k]) / (pb->nvel[k] - 1);
   }
+  g.tabw = pb->nvel[0] + pb->nvel[1] + pb->nvel[2];
   g.ne = s->L.ne;
   g.nx = s->L.nx;
   g.nv = s->L.nv;
