@@ -143,6 +143,39 @@ def cpu_baseline(pb_full, prim_fn, budget_s=12.0):
                       f"direct velocity sums"}
 
 
+def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4):
+    """Serving mix (shock tubes and periodic boxes, p in 1..3, 8^3..32^3 velocities,
+    Kn log-uniform [1e-4, 1], 100 steps each). A saturating run (all requests at
+    t = 0) measures the capacity; then the same requests arrive as a Poisson
+    stream at 0.8 x that rate. The comparator is the plain FP64 path: the same
+    kernels, one request at a time, no overlap, on the same two arrival
+    patterns (latency from the resulting queue)."""
+    from paper_2308_06196_amd import serve
+    from paper_2308_06196_amd import workloads as wl
+    pool = int(pool_gb * (1 << 30))
+
+    def reqs(rate):
+        return serve.make_requests(wl.serving_requests(n=n_requests, seed=seed, rate=rate,
+                                                       steps=steps))
+
+    def batched(rate):
+        ex = serve.BatchExecutor(max_members=max_members)
+        m = serve.Server(ex, pool, max_members=max_members, quantum=quantum).run(reqs(rate))
+        ex.close()
+        return m
+
+    sat = batched(None)
+    cap_rate = sat["completed"] / sat["span_s"]
+    pois = batched(0.8 * cap_rate)
+    seq_sat = serve.run_sequential(reqs(None))
+    seq_pois = serve.run_sequential(reqs(0.8 * cap_rate))
+    return {"requests": n_requests, "steps_each": steps,
+            "total_dof": int(sum(r.dof for r in reqs(None))),
+            "capacity_requests_per_s": cap_rate, "poisson_rate_per_s": 0.8 * cap_rate,
+            "batched_saturating": sat, "batched_poisson": pois,
+            "sequential_fp64_saturating": seq_sat, "sequential_fp64_poisson": seq_pois}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +186,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline value")
+    ap.add_argument("--serving", type=int, default=24, metavar="N",
+                    help="requests in the serving mix (0: skip)")
+    ap.add_argument("--serving-steps", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "calibrates the HBM byte counters against a known traffic")
@@ -191,6 +227,15 @@ def main():
               f"{mx['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         line["mixed"] = {"dtype": "f32-bulk/f64-collision", "value": mx["value"],
                          "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps)}
+    if a.serving:
+        sv = serving(a.serving, a.serving_steps)
+        line["serving"] = sv
+        p, q = sv["batched_poisson"], sv["sequential_fp64_poisson"]
+        print(f"[bench] serving {a.serving} requests: batched p50 {p['p50_s']:.3f} s, p99 "
+              f"{p['p99_s']:.3f} s (sequential FP64 p50 {q['p50_s']:.3f} s, p99 {q['p99_s']:.3f} s);"
+              f" saturating {sv['batched_saturating']['dof_updates_per_s']:.3e} vs "
+              f"{sv['sequential_fp64_saturating']['dof_updates_per_s']:.3e} DOF-updates/s",
+              file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, prim_fn)
         print(f"[bench] cpu baseline {line['cpu_baseline']}", file=sys.stderr, flush=True)

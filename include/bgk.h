@@ -147,8 +147,13 @@ bgk_status bgk_query_footprint(const bgk_problem* pb, size_t* workspace_bytes, i
 bgk_status bgk_create(const bgk_problem* pb, void* d_workspace, size_t bytes, void* hip_stream,
                       bgk_solver** out);
 
-/* Release the host-side solver object; never touches the workspace. */
+/* Release the host-side solver object; never touches the workspace.
+ * BGK_ERR_STATE (nothing released) while the solver is a batch member. */
 bgk_status bgk_destroy(bgk_solver* s);
+
+/* Move the solver to another HIP stream (NULL = default stream) after
+ * waiting for the work queued on the current one. Not for batch members. */
+bgk_status bgk_set_stream(bgk_solver* s, void* hip_stream);
 
 /* Solution-node coordinates into host x[nx][dim] (Gauss-Legendre points
  * mapped to each element; Sec. 2.1 nodal expansion). */
@@ -218,6 +223,50 @@ bgk_status bgk_timing_read(bgk_solver* s, bgk_timing* out);
 
 /* Wait for the solver's queued work and report any numerical failure. */
 bgk_status bgk_synchronize(bgk_solver* s);
+
+/* ------------------------------------------------------------------------
+ * Batches (serving): resident solvers advanced together. A replay is one
+ * launch of a captured HIP graph in which every member's kernels (the same
+ * kernels as bgk_rk3_step) form an independent branch: the member that
+ * moves the most bytes per step takes one RK3 step per replay, a member
+ * moving W times fewer takes the largest power of two <= W steps (at most
+ * its remaining ones), so small requests are not paced by the largest.
+ * Members never exchange data, so each member's result is bitwise the one
+ * it gets alone. Membership changes (add, completion, remove) re-capture the
+ * graph before the next replay. A batch does not own its members: the caller
+ * keeps every solver and its workspace alive until the solver has been
+ * polled or removed, then may destroy it.
+ * ------------------------------------------------------------------------ */
+typedef struct bgk_batch bgk_batch;
+
+/* Create a batch on hip_stream (NULL = default stream) with room for
+ * max_members (1..4096) concurrent members. Host-only allocation. */
+bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, bgk_batch** out);
+
+/* Add solver s (state installed, created on the batch's stream, timing off,
+ * not in another batch) to advance nsteps >= 1 steps of size dt.
+ * BGK_ERR_OUT_OF_MEMORY when the batch is full. */
+bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps);
+
+/* Queue nsteps graph replays (see above; a member stops after its own step
+ * count and becomes pollable). Asynchronous on the batch stream. */
+bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps);
+
+/* Synchronise with the batch stream and hand back up to cap members that
+ * have completed their steps: done[i] and its status status[i] (BGK_OK or
+ * the member's numerical failure). They leave the batch; *ndone is the
+ * count. */
+bgk_status bgk_batch_poll(bgk_batch* b, bgk_solver** done, int32_t* status, int32_t cap,
+                          int32_t* ndone);
+
+/* Remove an active member before completion (waits for queued work). */
+bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s);
+
+/* Number of active members (0 for NULL). */
+int32_t bgk_batch_size(const bgk_batch* b);
+
+/* Wait for queued work and release the batch (members are not touched). */
+bgk_status bgk_batch_destroy(bgk_batch* b);
 
 const char* bgk_status_str(bgk_status st);
 const char* bgk_last_error(void);

@@ -88,7 +88,8 @@ _lib = None
 def exported_names() -> list:
     """Function names declared in include/bgk.h."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:bgk_status|const char\*)\s+(bgk_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:bgk_status|const char\*|int32_t)\s+(bgk_\w+)\s*\(", txt,
+                                 re.M)))
 
 
 def lib():
@@ -117,11 +118,20 @@ def lib():
             "bgk_synchronize": [vp],
             "bgk_timing_enable": [vp, i32],
             "bgk_timing_read": [vp, C.POINTER(Timing)],
+            "bgk_set_stream": [vp, vp],
+            "bgk_batch_create": [vp, i32, C.POINTER(vp)],
+            "bgk_batch_add": [vp, vp, C.c_double, C.c_int64],
+            "bgk_batch_step": [vp, i32],
+            "bgk_batch_poll": [vp, C.POINTER(vp), C.POINTER(i32), i32, C.POINTER(i32)],
+            "bgk_batch_remove": [vp, vp],
+            "bgk_batch_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.bgk_batch_size.argtypes = [vp]
+        L.bgk_batch_size.restype = C.c_int32
         L.bgk_status_str.argtypes = [C.c_int]
         L.bgk_status_str.restype = C.c_char_p
         L.bgk_last_error.argtypes = []
@@ -171,8 +181,10 @@ class Solver:
     # -- lifetime ------------------------------------------------------------
     def close(self):
         if self._s:
-            lib().bgk_destroy(self._s)
+            _check(lib().bgk_destroy(self._s))
             self._s = C.c_void_p()
+            # queued work on the solver's stream may still use the workspace
+            self.stream.synchronize()
             self.workspace = None
 
     def __del__(self):
@@ -267,6 +279,10 @@ class Solver:
     def synchronize(self):
         _check(lib().bgk_synchronize(self._s))
 
+    def set_stream(self, stream):
+        _check(lib().bgk_set_stream(self._s, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def timing(self, on: bool):
         _check(lib().bgk_timing_enable(self._s, 1 if on else 0))
 
@@ -274,3 +290,54 @@ class Solver:
         t = Timing()
         _check(lib().bgk_timing_read(self._s, C.byref(t)))
         return t.as_dict()
+
+
+class Batch:
+    """Resident solvers advanced together by graph replay (libbgk batch C-ABI).
+    Members must be created on the batch's stream."""
+
+    def __init__(self, stream, max_members: int = 64):
+        self.stream = stream
+        self.max_members = max_members
+        self._b = C.c_void_p()
+        _check(lib().bgk_batch_create(C.c_void_p(stream.cuda_stream), int(max_members),
+                                      C.byref(self._b)))
+        self._members = {}
+
+    def add(self, solver: Solver, dt: float, nsteps: int):
+        _check(lib().bgk_batch_add(self._b, solver._s, float(dt), int(nsteps)))
+        self._members[solver._s.value] = solver
+
+    def step(self, nsteps: int):
+        _check(lib().bgk_batch_step(self._b, int(nsteps)))
+
+    def size(self) -> int:
+        return int(lib().bgk_batch_size(self._b))
+
+    def poll(self):
+        """[(solver, None | error message)] of members that completed."""
+        cap = max(1, len(self._members))
+        done = (C.c_void_p * cap)()
+        st = (C.c_int32 * cap)()
+        n = C.c_int32(0)
+        _check(lib().bgk_batch_poll(self._b, done, st, cap, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            s = self._members.pop(done[i])
+            out.append((s, None if st[i] == 0 else STATUS.get(st[i], str(st[i]))))
+        return out
+
+    def remove(self, solver: Solver):
+        _check(lib().bgk_batch_remove(self._b, solver._s))
+        self._members.pop(solver._s.value, None)
+
+    def close(self):
+        if self._b:
+            lib().bgk_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -20,7 +20,7 @@ namespace bgk {
 // E_c[b] = exp(alpha_{1+c} u_b + alpha_4 u_b^2 / 2): O(3 N_1d) work per node.
 // ---------------------------------------------------------------------------
 __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
-  double L[5][5];
+  double L[5][5], R[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
@@ -35,8 +35,9 @@ __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
       if (i == k) {
         if (!(s > 0.0)) return 1;
         L[i][i] = sqrt(s);
+        R[i] = 1.0 / L[i][i];
       } else {
-        L[i][k] = s / L[k][k];
+        L[i][k] = s * R[k];
       }
     }
   }
@@ -46,23 +47,26 @@ __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
     double s = b[i];
 #pragma unroll
     for (int m = 0; m < i; ++m) s -= L[i][m] * y[m];
-    y[i] = s / L[i][i];
+    y[i] = s * R[i];
   }
 #pragma unroll
   for (int i = 4; i >= 0; --i) {
     double s = y[i];
 #pragma unroll
     for (int m = i + 1; m < 5; ++m) s -= L[m][i] * x[m];
-    x[i] = s / L[i][i];
+    x[i] = s * R[i];
   }
   return 0;
 }
 
-// All-reduce of one FP64 value over the 16 lanes of a team (fixed order;
-// every lane ends with the same bits).
+// All-reduce of one FP64 value over the 16 lanes of a team (one DPP row):
+// partners lane ^ 8, the mirror inside 8 lanes, lane ^ 2, lane ^ 1. Each
+// step pairs lanes symmetrically, so every lane ends with the same bits.
 __device__ __forceinline__ double team_sum(double x) {
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) x += __shfl_xor(x, o, 16);
+  x += dpp_partner<8>(x);
+  x += dpp_partner<4>(x);
+  x += dpp_partner<2>(x);
+  x += dpp_partner<1>(x);
   return x;
 }
 
@@ -81,9 +85,20 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   const int64_t node = active ? node_raw : g.nx - 1;
   double Q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const double* pp = A.partials + node * g.nchunk * 5;
-  for (int c = r; c < g.nchunk; c += kTeam)
+  // chunk partials: batches of 4 chunks per lane, all loads of a batch in flight
+  for (int c0 = 0; c0 < g.nchunk; c0 += 4 * kTeam) {
+    double v[4][5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) Q[m] += pp[c * 5 + m];
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * kTeam + r;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) v[u][m] = c < g.nchunk ? pp[c * 5 + m] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Q[m] += v[u][m];
+  }
 #pragma unroll
   for (int m = 0; m < 5; ++m) Q[m] = team_sum(Q[m]);
   if (A.Q && r == 0 && active) {
@@ -107,7 +122,8 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   if (!(rho > 0.0) || !(th > 0.0)) {
     status = 2;
   } else {
-    al[0] = log(rho / pow(2.0 * M_PI * th, 1.5)) - UU / (2.0 * th);
+    const double tpt = 2.0 * M_PI * th;
+    al[0] = log(rho / (tpt * sqrt(tpt))) - UU / (2.0 * th);
     al[1] = Q[1] / rho / th;
     al[2] = Q[2] / rho / th;
     al[3] = Q[3] / rho / th;
@@ -138,9 +154,12 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
       }
       double m[3][5];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c) {
+        const double inv = 1.0 / S[c][0];
+        m[c][0] = 1.0;
 #pragma unroll
-        for (int n = 0; n < 5; ++n) m[c][n] = S[c][n] / S[c][0];
+        for (int n = 1; n < 5; ++n) m[c][n] = S[c][n] * inv;
+      }
       const double A0 = exp(al[0]) * S[0][0] * S[1][0] * S[2][0];
       double G[5], J[5][5];
       G[0] = A0;
@@ -259,19 +278,23 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const 
 
 // Continuous Maxwellian sampled at every (node, velocity); one work-group =
 // one node x one velocity chunk.
+// grid-stride over (node, velocity chunk) work items: the number of work
+// items can exceed what one launch dimension holds
 template <typename ST>
 __global__ void __launch_bounds__(kBlock) k_maxwellian(const DevGeom g, const double* prim, ST* f) {
-  const int64_t w = blockIdx.x;
-  const int64_t node = w / g.nchunk;
-  const int chunk = (int)(w % g.nchunk);
-  const int j = chunk * kBlock + (int)threadIdx.x;
-  if (j >= g.nv) return;
-  const Vel v = velocity_of(g, j);
-  const double* q = prim + node * 5;
-  const double rho = q[0], th = q[4];
-  const double nrm = rho / pow(2.0 * M_PI * th, 1.5);
-  const double dx = v.u[0] - q[1], dy = v.u[1] - q[2], dz = v.u[2] - q[3];
-  f[node * g.nv + j] = (ST)(nrm * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * th)));
+  const int64_t nw = g.nx * g.nchunk;
+  for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+    const int64_t node = w / g.nchunk;
+    const int chunk = (int)(w % g.nchunk);
+    const int j = chunk * kBlock + (int)threadIdx.x;
+    if (j >= g.nv) continue;
+    const Vel v = velocity_of(g, j);
+    const double* q = prim + node * 5;
+    const double rho = q[0], th = q[4];
+    const double nrm = rho / pow(2.0 * M_PI * th, 1.5);
+    const double dx = v.u[0] - q[1], dy = v.u[1] - q[2], dz = v.u[2] - q[3];
+    f[node * g.nv + j] = (ST)(nrm * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * th)));
+  }
 }
 
 template <typename SRC, typename DST>
@@ -330,7 +353,7 @@ hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, doub
 
 hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,
                              hipStream_t s) {
-  const dim3 grid((unsigned)(g.nx * g.nchunk));
+  const dim3 grid((unsigned)std::min<int64_t>(g.nx * g.nchunk, 1 << 20));
   if (precision == 0)
     hipLaunchKernelGGL(k_maxwellian<double>, grid, dim3(kBlock), 0, s, g, prim, (double*)f);
   else

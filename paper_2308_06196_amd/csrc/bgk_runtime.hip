@@ -254,6 +254,7 @@ struct bgk_solver {
   bool partials_valid = false;
   bool failed = false;
   bool counters_ready = false;  // device counters cleared since create
+  bool in_batch = false;
   double gamma;
   // event timing of rk3_step launches: events[i] .. events[i+1] brackets
   // interval i of kind kinds[i] (0 newton, 1 stage, 2 host gap)
@@ -429,7 +430,9 @@ bgk_status bgk_query_footprint(const bgk_problem* pb, size_t* bytes, int64_t* nx
   bgk_status st = validate(pb);
   if (st) return st;
   Layout L = layout_of(pb);
-  if ((double)L.nchunk * (double)L.ne >= 4294967295.0 || (double)L.nx * L.nchunk >= 2147483647.0)
+  // one launch dimension holds < 2^32 work-items (threads)
+  if ((double)L.nchunk * (double)L.ne * kBlock >= 4294967296.0 ||
+      (double)L.nx * 16.0 >= 4294967296.0)
     return fail(BGK_ERR_UNSUPPORTED, "problem too large for one launch grid");
   if (bytes) *bytes = L.total;
   if (nx) *nx = L.nx;
@@ -481,9 +484,22 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
 }
 
 bgk_status bgk_destroy(bgk_solver* s) {
+  if (s && s->in_batch) return fail(BGK_ERR_STATE, "solver is a batch member; remove or poll it");
   if (s)
     for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
   delete s;
+  return BGK_OK;
+}
+
+bgk_status bgk_set_stream(bgk_solver* s, void* hip_stream) {
+  if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
+  if (s->in_batch) return fail(BGK_ERR_STATE, "solver is a batch member");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (s->timing) {
+    s->used = 0;
+    s->kinds.clear();
+  }
+  s->stream = (hipStream_t)hip_stream;
   return BGK_OK;
 }
 
@@ -629,44 +645,60 @@ bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_
   return check_failed(s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Queue nsteps SSP-RK3 steps of one solver on stream st (the partials of the
+// state must be valid). Timing marks only when `timed` (never under capture).
+bgk_status rk3_launch(bgk_solver* s, double dt, int32_t nsteps, hipStream_t st, bool timed) {
+  static const double kA[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double kB[3] = {1.0, 0.25, 2.0 / 3.0};
+  bgk_status rc;
+  NewtonArgs N = newton_args(s);
+  N.Q = nullptr;
+  StageArgs A = stage_args(s);
+  A.dt = dt;
+  A.fn = s->f(0);
+  if (timed) {
+    if (s->used > 0) s->kinds.push_back(2);  // host gap between calls: not a kernel
+    if ((rc = mark(s))) return rc;
+  }
+  for (int32_t step = 0; step < nsteps; ++step) {
+    for (int k = 0; k < 3; ++k) {
+      HIP_TRY(launch_newton(N, st));
+      if (timed) {
+        s->kinds.push_back(0);
+        if ((rc = mark(s))) return rc;
+      }
+      A.fin = s->f(k);
+      A.out = s->f((k + 1) % 3);
+      A.a = kA[k];
+      A.b = kB[k];
+      HIP_TRY(launch_stage(s->precision, 0, A, st));
+      if (timed) {
+        s->kinds.push_back(1);
+        if ((rc = mark(s))) return rc;
+      }
+    }
+  }
+  return BGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 bgk_status bgk_rk3_step(bgk_solver* s, double dt, int32_t nsteps) {
   if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
   if (!(dt > 0.0) || !isfinite(dt)) return fail(BGK_ERR_INVALID_ARG, "dt must be > 0");
   if (nsteps < 0) return fail(BGK_ERR_INVALID_ARG, "nsteps < 0");
   if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
   if (s->failed) return fail(BGK_ERR_STATE, "solver failed earlier; install a new state");
+  if (s->in_batch) return fail(BGK_ERR_STATE, "solver is a batch member; step the batch");
   bgk_status st = ensure_partials(s);
   if (st) return st;
-  static const double kA[3] = {0.0, 0.75, 1.0 / 3.0};
-  static const double kB[3] = {1.0, 0.25, 2.0 / 3.0};
-  NewtonArgs N = newton_args(s);
-  N.Q = nullptr;
-  StageArgs A = stage_args(s);
-  A.dt = dt;
-  A.fn = s->f(0);
-  if (s->timing) {
-    if (s->used > 0) s->kinds.push_back(2);  // host gap between calls: not a kernel
-    if ((st = mark(s))) return st;
-  }
-  for (int32_t step = 0; step < nsteps; ++step) {
-    for (int k = 0; k < 3; ++k) {
-      HIP_TRY(launch_newton(N, s->stream));
-      if (s->timing) {
-        s->kinds.push_back(0);
-        if ((st = mark(s))) return st;
-      }
-      A.fin = s->f(k);
-      A.out = s->f((k + 1) % 3);
-      A.a = kA[k];
-      A.b = kB[k];
-      HIP_TRY(launch_stage(s->precision, 0, A, s->stream));
-      if (s->timing) {
-        s->kinds.push_back(1);
-        if ((st = mark(s))) return st;
-      }
-    }
-  }
-  return BGK_OK;
+  return rk3_launch(s, dt, nsteps, s->stream, s->timing);
 }
 
 bgk_status bgk_timing_enable(bgk_solver* s, int32_t on) {
@@ -775,6 +807,211 @@ bgk_status bgk_diagnostics(bgk_solver* s, bgk_diag* out) {
 bgk_status bgk_synchronize(bgk_solver* s) {
   if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
   return check_failed(s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: resident solvers advanced together by replaying one captured
+// graph, in which every member's kernels (a few RK3 steps each) form an
+// independent branch (fork/join events on the batch stream). A change of
+// membership re-captures the graph before the next replay.
+// ---------------------------------------------------------------------------
+struct bgk_batch {
+  hipStream_t stream;
+  int32_t max_members;
+  struct Member {
+    bgk_solver* s;
+    double dt;
+    int64_t remaining;
+    int64_t per_replay;  // steps per graph replay (set at capture)
+  };
+  std::vector<Member> members;
+  std::vector<bgk_solver*> finished;  // stepped to completion, not yet polled
+  std::vector<hipStream_t> branches;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;
+};
+
+namespace {
+
+bgk_status batch_capture(bgk_batch* b) {
+  if (b->exec) {
+    HIP_TRY(hipGraphExecDestroy(b->exec));
+    b->exec = nullptr;
+  }
+  const size_t n = b->members.size();
+  while (b->branches.size() < n) {
+    hipStream_t st;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b->branches.push_back(st);
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->joins.push_back(ev);
+  }
+  if (n == 0) {
+    b->dirty = false;
+    return BGK_OK;
+  }
+  // Work balance: the member moving the most bytes per step takes one step
+  // per replay; a member moving W times fewer takes the largest power of two
+  // <= W (at most its remaining steps), so small requests are not paced by
+  // the largest one.
+  double wmax = 0.0;
+  for (auto& m : b->members) wmax = std::max(wmax, (double)m.s->L.fbytes);
+  for (auto& m : b->members) {
+    const double ratio = wmax / std::max(1.0, (double)m.s->L.fbytes);
+    int64_t k = 1;
+    while (2.0 * k <= ratio && 2 * k <= m.remaining && k < 1024) k *= 2;
+    m.per_replay = std::min<int64_t>(k, m.remaining);
+  }
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  bgk_status rc = BGK_OK;
+  hipError_t e = hipEventRecord(b->fork, b->stream);
+  for (size_t i = 0; i < n && e == hipSuccess && rc == BGK_OK; ++i) {
+    e = hipStreamWaitEvent(b->branches[i], b->fork, 0);
+    if (e != hipSuccess) break;
+    rc = rk3_launch(b->members[i].s, b->members[i].dt, (int32_t)b->members[i].per_replay,
+                    b->branches[i], false);
+    if (rc) break;
+    e = hipEventRecord(b->joins[i], b->branches[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->joins[i], 0);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(BGK_ERR_DEVICE, "graph capture: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(BGK_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  b->dirty = false;
+  return BGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, bgk_batch** out) {
+  if (!out) return fail(BGK_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_members < 1 || max_members > 4096)
+    return fail(BGK_ERR_INVALID_ARG, "max_members must be in 1..4096");
+  bgk_batch* b = new (std::nothrow) bgk_batch();
+  if (!b) return fail(BGK_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->stream = (hipStream_t)hip_stream;
+  b->max_members = max_members;
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(BGK_ERR_DEVICE, "event: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return BGK_OK;
+}
+
+bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps) {
+  if (!b || !s) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(BGK_ERR_INVALID_ARG, "dt must be > 0");
+  if (nsteps < 1) return fail(BGK_ERR_INVALID_ARG, "nsteps < 1");
+  if ((int32_t)b->members.size() >= b->max_members)
+    return fail(BGK_ERR_OUT_OF_MEMORY, "batch is full (%d members)", b->max_members);
+  if (s->stream != b->stream) return fail(BGK_ERR_INVALID_ARG, "solver and batch streams differ");
+  if (s->in_batch) return fail(BGK_ERR_STATE, "solver already in a batch");
+  if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+  if (s->failed) return fail(BGK_ERR_STATE, "solver failed earlier; install a new state");
+  if (s->timing) return fail(BGK_ERR_STATE, "disable timing before adding to a batch");
+  bgk_status st = ensure_partials(s);
+  if (st) return st;
+  s->in_batch = true;
+  b->members.push_back({s, dt, nsteps, 1});
+  b->dirty = true;
+  return BGK_OK;
+}
+
+bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps) {
+  if (!b) return fail(BGK_ERR_INVALID_ARG, "NULL batch");
+  if (nsteps < 0) return fail(BGK_ERR_INVALID_ARG, "nsteps < 0");
+  for (int32_t k = 0; k < nsteps && !b->members.empty(); ++k) {
+    if (b->dirty) {
+      bgk_status st = batch_capture(b);
+      if (st) return st;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    size_t w = 0;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+      bgk_batch::Member& m = b->members[i];
+      m.remaining -= m.per_replay;
+      if (m.remaining == 0) {
+        b->finished.push_back(m.s);
+        b->dirty = true;
+      } else {
+        if (m.per_replay > m.remaining) b->dirty = true;  // re-balance near the end
+        b->members[w++] = m;
+      }
+    }
+    b->members.resize(w);
+  }
+  return BGK_OK;
+}
+
+bgk_status bgk_batch_poll(bgk_batch* b, bgk_solver** done, int32_t* status, int32_t cap,
+                          int32_t* ndone) {
+  if (!b || !ndone || (cap > 0 && (!done || !status)))
+    return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  *ndone = 0;
+  if (b->finished.empty()) return BGK_OK;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int32_t n = 0;
+  size_t i = 0;
+  for (; i < b->finished.size() && n < cap; ++i) {
+    bgk_solver* s = b->finished[i];
+    s->in_batch = false;
+    done[n] = s;
+    status[n] = (int32_t)check_failed(s);
+    ++n;
+  }
+  b->finished.erase(b->finished.begin(), b->finished.begin() + i);
+  *ndone = n;
+  return BGK_OK;
+}
+
+bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s) {
+  if (!b || !s) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    if (b->members[i].s == s) {
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      s->in_batch = false;
+      b->members.erase(b->members.begin() + i);
+      b->dirty = true;
+      return BGK_OK;
+    }
+  }
+  return fail(BGK_ERR_INVALID_ARG, "solver is not an active member");
+}
+
+int32_t bgk_batch_size(const bgk_batch* b) { return b ? (int32_t)b->members.size() : 0; }
+
+bgk_status bgk_batch_destroy(bgk_batch* b) {
+  if (!b) return BGK_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (auto& m : b->members) m.s->in_batch = false;
+  for (auto* s : b->finished) s->in_batch = false;
+  for (hipStream_t st : b->branches) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->joins) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+  return BGK_OK;
 }
 
 }  // extern "C"

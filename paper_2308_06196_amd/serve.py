@@ -1,0 +1,221 @@
+"""Continuous-batching request loop for BGK solves (serving pattern).
+
+Requests (shock tubes, periodic boxes, ...) arrive over time. The server
+admits them, oldest first, as soon as their device-memory footprint fits the
+pool and a member slot is free; admitted requests stay resident and advance
+together: each quantum replays one captured graph per RK3 step in which every
+member's kernels form an independent branch, so their work overlaps on the
+device. Finished requests free their memory and slot for waiting ones.
+Latency = completion - arrival; p50/p99 and aggregate DOF-updates/s are
+reported.
+
+The scheduling logic is independent of the device: `Server` drives any object
+with the `Executor` interface. `BatchExecutor` is the GPU one (libbgk batch
+C-ABI); tests drive `Server` with a CPU stand-in.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    problem: dict
+    kind: str
+    prim_args: dict
+    arrival: float
+    steps: int
+    precision: int = 0
+    # filled by the server
+    footprint: int = 0
+    dof: int = 0
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    failed: Optional[str] = None
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done is None else self.done - self.arrival
+
+
+class Executor:
+    """Device side of the server. `admit` allocates and initialises one request
+    and makes it a batch member; `step(n)` advances every member by up to n
+    steps (members stop at their own step count); `poll` returns the handles
+    of members that have completed (after waiting for queued work) as pairs
+    (handle, error or None); `release` frees a completed member."""
+
+    def footprint(self, req: Request) -> int: ...
+    def admit(self, req: Request): ...
+    def step(self, n: int) -> None: ...
+    def poll(self) -> list: ...
+    def release(self, handle) -> None: ...
+
+
+class Server:
+    def __init__(self, executor: Executor, capacity_bytes: int, max_members: int = 64,
+                 quantum: int = 10, clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.ex = executor
+        self.capacity = int(capacity_bytes)
+        self.max_members = int(max_members)
+        self.quantum = int(quantum)
+        self.clock = clock
+        self.sleep = sleep
+        self.used = 0
+        self.active = {}  # handle -> Request
+
+    def run(self, requests: List[Request]) -> dict:
+        pending = sorted(requests, key=lambda r: (r.arrival, r.id))
+        for r in pending:
+            r.footprint = int(self.ex.footprint(r))
+            if r.footprint > self.capacity:
+                r.failed = "footprint exceeds the pool"
+        pending = [r for r in pending if r.failed is None]
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        finished: List[Request] = []
+        while pending or self.active:
+            t = now()
+            # admission: oldest arrived request first, while memory and slots allow
+            while (pending and pending[0].arrival <= t and len(self.active) < self.max_members
+                   and self.used + pending[0].footprint <= self.capacity):
+                r = pending.pop(0)
+                try:
+                    h = self.ex.admit(r)
+                except Exception as exc:  # a request that cannot start fails alone
+                    r.failed = f"admit: {exc}"
+                    finished.append(r)
+                    continue
+                r.admitted = now()
+                self.used += r.footprint
+                self.active[h] = r
+            if not self.active:
+                if pending:
+                    wait = pending[0].arrival - now()
+                    if wait > 0:
+                        self.sleep(wait)
+                continue
+            self.ex.step(self.quantum)
+            for h, err in self.ex.poll():
+                r = self.active.pop(h)
+                r.done = now()
+                if err:
+                    r.failed = str(err)
+                self.used -= r.footprint
+                self.ex.release(h)
+                finished.append(r)
+        return metrics(finished + [r for r in requests if r.failed and r not in finished])
+
+
+def metrics(reqs: List[Request]) -> dict:
+    ok = [r for r in reqs if r.failed is None and r.done is not None]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(0)
+    work = float(sum(r.dof * r.steps for r in ok))
+    span = (max(r.done for r in ok) - min(r.arrival for r in ok)) if ok else 0.0
+    waits = np.array([r.admitted - r.arrival for r in ok]) if ok else np.zeros(0)
+    return {
+        "requests": len(reqs), "completed": len(ok), "failed": len(reqs) - len(ok),
+        "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        "mean_admission_wait_s": float(waits.mean()) if len(waits) else None,
+        "dof_updates": work, "span_s": span,
+        "dof_updates_per_s": work / span if span > 0 else None,
+    }
+
+
+def make_requests(descs, precision: int = 0) -> List[Request]:
+    """Request objects from workloads.serving_requests descriptors."""
+    out = []
+    for d in descs:
+        pb = d["problem"]
+        ne = int(np.prod(pb["nelem"][: pb["dim"]]))
+        dof = ne * (pb["order"] + 1) ** pb["dim"] * int(np.prod(pb["nvel"]))
+        out.append(Request(id=d["id"], problem=pb, kind=d["kind"], prim_args=d["prim_args"],
+                           arrival=d["arrival"], steps=d["steps"], precision=precision, dof=dof))
+    return out
+
+
+class BatchExecutor(Executor):
+    """GPU executor over the libbgk batch C-ABI. Each member owns a torch
+    workspace; all members run on the batch's stream (captured graph with one
+    branch per member)."""
+
+    def __init__(self, device="cuda:0", max_members: int = 64, cfl: float = 0.1):
+        import torch
+
+        from . import bgk
+        from . import workloads as wl
+        self.torch, self.bgk, self.wl = torch, bgk, wl
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.init_stream = torch.cuda.Stream(device=device)
+        self.device = device
+        self.cfl = cfl
+        self.batch = bgk.Batch(self.stream, max_members)
+        self.members = {}
+
+    def footprint(self, req: Request) -> int:
+        return self.bgk.footprint(req.problem, req.precision)[0]
+
+    def admit(self, req: Request):
+        # initialise on a side stream (its synchronisation does not wait for
+        # the members already running), then move to the batch stream
+        s = self.bgk.Solver(req.problem, precision=req.precision, device=self.device,
+                            stream=self.init_stream)
+        s.set_maxwellian(self.wl.PRIM[req.kind](s.node_coords(), **req.prim_args))
+        dt = s.stable_dt(self.cfl)
+        s.set_stream(self.stream)
+        self.batch.add(s, dt, req.steps)
+        self.members[id(s)] = s
+        return id(s)
+
+    def step(self, n: int) -> None:
+        self.batch.step(n)
+
+    def poll(self) -> list:
+        out = []
+        for s, err in self.batch.poll():
+            out.append((id(s), err))
+        return out
+
+    def release(self, handle) -> None:
+        s = self.members.pop(handle)
+        s.close()
+
+    def close(self):
+        self.batch.close()
+
+
+def run_sequential(requests: List[Request], device="cuda:0", cfl: float = 0.1) -> dict:
+    """The plain path for comparison: one request at a time, FP64 kernels, no
+    overlap; latency measured as if all requests were queued at their arrival
+    time behind the previous ones."""
+    import torch
+
+    from . import bgk
+    from . import workloads as wl
+    t0 = time.perf_counter()
+    clock = 0.0
+    for r in sorted(requests, key=lambda r: (r.arrival, r.id)):
+        start = max(clock, r.arrival)
+        s = bgk.Solver(r.problem, precision=r.precision, device=device)
+        s.set_maxwellian(wl.PRIM[r.kind](s.node_coords(), **r.prim_args))
+        dt = s.stable_dt(cfl)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s.rk3_step(dt, r.steps)
+        s.synchronize()
+        el = time.perf_counter() - a
+        s.close()
+        r.admitted = start
+        clock = start + el
+        r.done = clock
+    res = metrics(requests)
+    res["wall_s"] = time.perf_counter() - t0
+    return res

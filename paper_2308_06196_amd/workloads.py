@@ -153,6 +153,8 @@ def serving_requests(n=256, seed=0, rate=None, nv_choices=(8, 16, 24, 32), steps
     [0.01, 0.2]. Arrival times are Poisson with the given rate (all at 0 when
     rate is None)."""
     rng = np.random.default_rng(seed)
+    # arrivals from a stream of their own: the requests do not depend on the rate
+    rng_t = np.random.default_rng([seed, 7919])
     out = []
     t = 0.0
     for r in range(n):
@@ -171,7 +173,7 @@ def serving_requests(n=256, seed=0, rate=None, nv_choices=(8, 16, 24, 32), steps
             pb = box2d(n=ne1, order=order, nv1=nv1, kn=kn)
             prim_args = {"amp": amp}
         if rate:
-            t += float(rng.exponential(1.0 / rate))
+            t += float(rng_t.exponential(1.0 / rate))
         out.append({"id": r, "kind": kind, "problem": pb, "prim_args": prim_args,
                     "arrival": t if rate else 0.0, "steps": steps})
     return out

@@ -260,3 +260,36 @@ def test_numerical_failure_is_reported(torch):
     s.set_state(dev(torch, initial_state(pb, kind)))  # recovers
     s.rk3_step(1e-4, 1)
     s.synchronize()
+
+
+@pytest.mark.parametrize("name", ["d1p2_sod_spec", "d2p2_box", "d3p1_tgv", "d3p2_tgv",
+                                  "d3p3_tgv"])
+def test_fp32_rk3_matches_oracle(torch, name):
+    """FP32 storage / FP64 moments and Newton: 3 steps within 1e-5 of the FP64 oracle."""
+    pb, kind = CASES[name]
+    _say("rk3-fp32", name)
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, kind, seed=8, amp=0.2)
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb, precision=1)
+    s.set_state(dev(torch, f0))
+    s.rk3_step(dt, 3)
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 3)
+    assert rel_max(s.get_state().cpu().numpy(), f_orc) < 1e-5
+    s.diagnostics()
+
+
+def test_mach2_reduced_fp32_and_fp64(torch):
+    """Mach-2 box (3-D, p=2, 20^3 velocities on [-8,8]^3) on 3^3 elements, 2 steps."""
+    pb = wl.mach2(n=3)
+    _say("mach2-reduced", pb["nelem"])
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "mach2")
+    dt = orc.stable_dt(pr, f0, 0.1)
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 2)
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        s = solver(pb, precision=prec)
+        s.set_state(dev(torch, f0))
+        s.rk3_step(dt, 2)
+        assert rel_max(s.get_state().cpu().numpy(), f_orc) < tol, prec
+        s.diagnostics()

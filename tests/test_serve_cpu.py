@@ -1,0 +1,127 @@
+"""Serving scheduler logic against a CPU stand-in executor on a virtual clock:
+admission by footprint, FIFO order, continuous admission while others run,
+memory never over-committed, failures isolated to their request."""
+import numpy as np
+import pytest
+
+from paper_2308_06196_amd import serve
+from paper_2308_06196_amd import workloads as wl
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class FakeExecutor(serve.Executor):
+    """Members advance together; a step costs dof / rate seconds of virtual time
+    per member (the device is shared)."""
+
+    def __init__(self, clock, rate=1e9, fail_admit=(), fail_run=()):
+        self.clock, self.rate = clock, rate
+        self.fail_admit, self.fail_run = set(fail_admit), set(fail_run)
+        self.members = {}
+        self.used = 0
+        self.max_used = 0
+        self.order = []
+
+    def footprint(self, r):
+        return r.dof * 8 * 3
+
+    def admit(self, r):
+        if r.id in self.fail_admit:
+            raise RuntimeError("injected admission failure")
+        self.members[r.id] = [r, r.steps]
+        self.used += self.footprint(r)
+        self.max_used = max(self.max_used, self.used)
+        self.order.append(r.id)
+        return r.id
+
+    def step(self, n):
+        cost = 0.0
+        for h, m in self.members.items():
+            k = min(n, m[1])
+            m[1] -= k
+            cost += k * m[0].dof / self.rate
+        self.clock.t += cost
+
+    def poll(self):
+        out = []
+        for h, (r, left) in list(self.members.items()):
+            if left == 0:
+                out.append((h, "injected member failure" if h in self.fail_run else None))
+        return out
+
+    def release(self, h):
+        r, _ = self.members.pop(h)
+        self.used -= self.footprint(r)
+
+
+def _requests(n=40, rate=50.0, seed=0):
+    return serve.make_requests(wl.serving_requests(n=n, seed=seed, rate=rate,
+                                                   nv_choices=(8, 16), steps=20))
+
+
+def test_all_complete_and_memory_bounded():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    reqs = _requests()
+    cap = int(2.5 * max(ex.footprint(r) for r in reqs))
+    m = serve.Server(ex, cap, max_members=8, quantum=5, clock=clk, sleep=clk.sleep).run(reqs)
+    assert m["completed"] == len(reqs) and m["failed"] == 0
+    assert ex.max_used <= cap
+    assert m["p99_s"] >= m["p50_s"] > 0
+    for r in reqs:
+        assert r.done >= r.admitted >= r.arrival
+        assert r.done - r.arrival >= r.steps * r.dof / ex.rate * 0.999
+
+
+def test_fifo_admission_order():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    reqs = _requests(seed=3)
+    serve.Server(ex, 10 ** 15, max_members=4, quantum=5, clock=clk, sleep=clk.sleep).run(reqs)
+    by_arrival = [r.id for r in sorted(reqs, key=lambda r: (r.arrival, r.id))]
+    assert ex.order == by_arrival
+
+
+def test_requests_join_while_others_run():
+    clk = Clock()
+    ex = FakeExecutor(clk, rate=1e7)
+    reqs = _requests(n=20, rate=1000.0, seed=5)
+    serve.Server(ex, 10 ** 15, max_members=64, quantum=2, clock=clk, sleep=clk.sleep).run(reqs)
+    # some request is admitted after another one started but before it finished
+    spans = [(r.admitted, r.done) for r in reqs]
+    overlap = any(a1 < a2 < d1 for (a1, d1) in spans for (a2, _) in spans)
+    assert overlap
+
+
+def test_oversized_and_failing_requests_are_isolated():
+    clk = Clock()
+    reqs = _requests(n=12, seed=7)
+    ex = FakeExecutor(clk, fail_admit={reqs[2].id}, fail_run={reqs[5].id})
+    big = max(reqs, key=lambda r: r.dof)
+    cap = ex.footprint(big) - 1  # the largest request cannot fit at all
+    m = serve.Server(ex, cap, max_members=8, quantum=5, clock=clk, sleep=clk.sleep).run(reqs)
+    failed = {r.id for r in reqs if r.failed}
+    assert {reqs[2].id, reqs[5].id, big.id} <= failed
+    assert m["completed"] == len(reqs) - len(failed)
+    assert ex.used == 0 and not ex.members
+
+
+def test_metrics_percentiles():
+    rs = []
+    for i, lat in enumerate([1.0, 2.0, 3.0, 4.0]):
+        r = serve.Request(id=i, problem={}, kind="x", prim_args={}, arrival=0.0, steps=1, dof=10)
+        r.admitted, r.done = 0.0, lat
+        rs.append(r)
+    m = serve.metrics(rs)
+    assert m["p50_s"] == pytest.approx(2.5)
+    assert m["p99_s"] == pytest.approx(np.percentile([1, 2, 3, 4], 99))
+    assert m["dof_updates_per_s"] == pytest.approx(40 / 4.0)
