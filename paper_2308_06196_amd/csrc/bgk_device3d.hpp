@@ -1,0 +1,458 @@
+// bgk_device3d.hpp -- stage and moment kernels for hexahedral (d = 3)
+// elements on gfx950 (Dzanic & Martinelli, arXiv 2308.06196, Sec. 2.1).
+//
+// A (p+1)^3-node element does not fit one lane's registers, so a group of
+// G lanes (G = 2 for p = 1, 4 for p = 2, 3) shares one velocity and lane g of
+// the group owns the z-plane a_z = g of the element: (p+1)^2 nodes. The x and
+// y operators are lane-local exactly as for quadrilaterals; the z-derivative
+// and the z-face traces need the other planes of the same column, which come
+// from the other lanes of the group by DPP quad permutations (no LDS, no
+// barriers). A work-group of 256 lanes covers 256 / G consecutive velocities
+// of one element. Lanes with g >= p+1 (p = 2) load nothing and store nothing.
+#pragma once
+
+#include "bgk_device.hpp"
+
+namespace bgk {
+
+template <int P> struct Plane3 {
+  static constexpr int N1 = P + 1;
+  static constexpr int G = N1 <= 2 ? 2 : 4;   // lanes per velocity
+  static constexpr int VB = kBlock / G;        // velocities per work-group
+  static constexpr int P2 = N1 * N1;           // nodes per plane
+  static constexpr int NS = N1 * N1 * N1;
+};
+
+// Value of lane b of this lane's group (G = 2 or 4 lanes inside a quad).
+template <int G, int B>
+__device__ __forceinline__ double group_bcast(double x) {
+  constexpr int ctrl = G == 4 ? (B | (B << 2) | (B << 4) | (B << 6))
+                              : (B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6));
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int G, int B>
+__device__ __forceinline__ float group_bcast(float x) {
+  constexpr int ctrl = G == 4 ? (B | (B << 2) | (B << 4) | (B << 6))
+                              : (B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+
+// Sum / min over the G lanes of a group (partners lane ^ 1, lane ^ 2; every
+// lane ends with the same bits).
+template <int G>
+__device__ __forceinline__ double group_allsum(double x) {
+  x += dpp_partner<1>(x);
+  if constexpr (G == 4) x += dpp_partner<2>(x);
+  return x;
+}
+template <int G>
+__device__ __forceinline__ float group_allsum(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+  if constexpr (G == 4)
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+  return x;
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_allmin(T x) {
+  T y = (T)dpp_partner<1>((double)x);
+  x = y < x ? y : x;
+  if constexpr (G == 4) {
+    y = (T)dpp_partner<2>((double)x);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+// Butterfly reduce-scatter over lane bits 5, 4, 3 only (partners keep the
+// low three lane bits, which hold the plane index): afterwards lanes that
+// differ only in bits 3..5 hold disjoint index ranges of their partial sums.
+template <int H, int STEP, int W>
+__device__ __forceinline__ void wave_level_hi(const double (&v)[H], double* lds_wave, int lane,
+                                              int base) {
+  if constexpr (STEP == 3) {
+    // lane keeps H values for indices base..base+H-1; slot (width W) by its
+    // low three lane bits
+#pragma unroll
+    for (int q = 0; q < H; ++q) lds_wave[(lane & 7) * W + base + q] = v[q];
+  } else {
+    constexpr int O = 32 >> STEP;
+    static_assert(H % 2 == 0, "reduction count must halve three times");
+    constexpr int HH = H / 2;
+    const bool up = (lane & O) != 0;
+    double w[HH];
+    if constexpr (O == 32 || O == 16) {
+#pragma unroll
+      for (int q = 0; q < HH; ++q) w[q] = swap_sum<O>(v[q], v[q + HH]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < HH; ++q) {
+        const double send = up ? v[q] : v[q + HH];
+        const double keep = up ? v[q + HH] : v[q];
+        w[q] = keep + dpp_partner<8>(send);
+      }
+    }
+    wave_level_hi<HH, STEP + 1, W>(w, lds_wave, lane, base + (up ? HH : 0));
+  }
+}
+
+// Moment partials of the lane's plane values (P2 nodes), velocity-chunk sums
+// into partials[(node)*nchunk + chunk][5]. Lanes outside the grid (or idle
+// planes) enter with w = 0. LDS: 4 waves x 8 low-lane slots x 64 doubles.
+template <int P>
+struct PlaneRed {
+  static constexpr int P2 = Plane3<P>::P2;
+  static constexpr int GN = P2 % 8 == 0 ? 8 : P2;  // nodes per reduction group
+  static constexpr int NGR = P2 / GN;
+  static constexpr int M = 5 * GN;
+  static constexpr int MP = (M + 7) / 8 * 8;         // halves three times
+  static constexpr int LDS = (kBlock / 64) * NGR * 8 * MP;
+};
+
+template <int P, typename CT>
+__device__ __forceinline__ void plane_partials(const CT (&fv)[Plane3<P>::P2], const Vel& vel,
+                                               double* __restrict__ partials, int64_t node0,
+                                               int nchunk, int chunk, int plane, double* red) {
+  using PL = Plane3<P>;
+  constexpr int P2 = PL::P2;
+  constexpr int G = PL::G;
+  using R = PlaneRed<P>;
+  constexpr int GN = R::GN, NGR = R::NGR, M = R::M, MP = R::MP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
+#pragma unroll
+  for (int gi = 0; gi < NGR; ++gi) {
+    double v[MP];
+#pragma unroll
+    for (int q = 0; q < GN; ++q) {
+      const double wf = vel.w * (double)fv[gi * GN + q];
+      v[5 * q + 0] = wf;
+      v[5 * q + 1] = wf * vel.u[0];
+      v[5 * q + 2] = wf * vel.u[1];
+      v[5 * q + 3] = wf * vel.u[2];
+      v[5 * q + 4] = wf * psi4;
+    }
+#pragma unroll
+    for (int q = M; q < MP; ++q) v[q] = 0.0;
+    wave_level_hi<MP, 0, MP>(v, red + (wave * NGR + gi) * 8 * MP, lane, 0);
+  }
+  __syncthreads();
+  // final sums: for each plane, node of the plane and moment, add the
+  // 4 waves x (8 / G) low-lane slots that hold that plane
+  constexpr int NOUT = PL::N1 * P2 * 5;
+  for (int t = threadIdx.x; t < NOUT; t += kBlock) {
+    const int pl = t / (P2 * 5), rest = t - pl * P2 * 5;
+    const int qn = rest / 5, m = rest - qn * 5;
+    const int gi = qn / GN, idx = (qn - gi * GN) * 5 + m;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w)
+#pragma unroll
+      for (int hi = 0; hi < 8 / G; ++hi) s += red[((w * NGR + gi) * 8 + hi * G + pl) * MP + idx];
+    partials[((node0 + pl * P2 + qn) * nchunk + chunk) * 5 + m] = s;
+  }
+  (void)plane;
+}
+
+
+template <int P, typename ST, int MODE>
+__global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
+  using CT = typename Compute<ST>::T;
+  using PL = Plane3<P>;
+  constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
+  __shared__ double red[PlaneRed<P>::LDS];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  CT* tab = reinterpret_cast<CT*>(dyn_lds);
+
+  const DevGeom& g = A.g;
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = (int)(w / A.ecount);
+  const int64_t e = A.e0 + (w % A.ecount);
+  const int64_t nv = g.nv;
+  const int S = g.tabw;
+  const int64_t node0 = e * NS;
+
+  const int lp = (int)threadIdx.x % G;           // plane owned by this lane
+  const bool live = lp < N1;
+  const int pl = live ? lp : N1 - 1;             // address plane (idle lanes)
+  const int j = chunk * VB + (int)threadIdx.x / G;
+  const bool valid = j < nv;
+  const bool act = valid && live;
+  const int jj = valid ? j : (int)nv - 1;
+  Vel vel = velocity_of(g, jj);
+  if (!act) vel.w = 0.0;
+
+  int ek[3];
+  {
+    int64_t r = e;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ek[k] = (int)(r % g.nelem[k]);
+      r /= g.nelem[k];
+    }
+  }
+  const ST* __restrict__ fin = (const ST*)A.fin;
+  const ST* src[3];
+  bool pos[3], use_right[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pos[k] = vel.u[k] * g.scale[k] > 0.0;
+    const int nek = sreg(g.nelem[k]);
+    const bool wall_lo = sreg(g.bc[k][0]) != 0, wall_hi = sreg(g.bc[k][1]) != 0;
+    int nk = ek[k] + (pos[k] ? -1 : 1);
+    bool wall = false;
+    if (nk < 0 || nk >= nek) {
+      wall = pos[k] ? wall_lo : wall_hi;
+      nk = (nk + nek) % nek;
+    }
+    int64_t src_e = e;
+    int src_j = jj;
+    if (wall) {
+      int bm[3] = {vel.b[0], vel.b[1], vel.b[2]};
+      bm[k] = g.nv1[k] - 1 - bm[k];
+      src_j = bm[0] + g.nv1[0] * (bm[1] + g.nv1[1] * bm[2]);
+    } else {
+      int64_t stride = 1;
+      for (int m = 0; m < k; ++m) stride *= g.nelem[m];
+      src_e = e + (int64_t)(nk - ek[k]) * stride;
+    }
+    use_right[k] = (pos[k] != wall);
+    src[k] = fin + (src_e * NS + pl * P2) * nv + src_j;
+  }
+
+  // loads: equilibrium factors and 1/tau (first batch), own plane, f^n
+  // plane, the x-, y- and z-neighbours' planes
+  constexpr int kU = 8;
+  const int ntab = NS * S;
+  const double* et = A.etab + node0 * S;
+  double tv[kU];
+  double itv = 0.0;
+  if (A.collide) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = u * kBlock + (int)threadIdx.x;
+      tv[u] = t < ntab ? et[t] : 0.0;
+    }
+    if (threadIdx.x < NS) itv = A.params[(node0 + threadIdx.x) * 8 + 5];
+  }
+  const ST* fe = fin + (node0 + pl * P2) * nv + jj;
+  CT f[P2];
+#pragma unroll
+  for (int q = 0; q < P2; ++q) f[q] = (CT)fe[(int64_t)q * nv];
+  CT fnv[P2];
+  if constexpr (MODE == 0) {
+    if (A.a != 0.0) {
+      const ST* fn = (const ST*)A.fn + (node0 + pl * P2) * nv + jj;
+#pragma unroll
+      for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[(int64_t)q * nv];
+    }
+  }
+  CT nb[3][P2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][(int64_t)q * nv];
+
+  CT* itau = tab + NS * S;
+  if (A.collide) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = u * kBlock + (int)threadIdx.x;
+      if (t < ntab) tab[t] = (CT)tv[u];
+    }
+    if (threadIdx.x < NS) itau[threadIdx.x] = (CT)itv;
+    for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int t = t0 + u * kBlock + (int)threadIdx.x;
+        v[u] = t < ntab ? et[t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int t = t0 + u * kBlock + (int)threadIdx.x;
+        if (t < ntab) tab[t] = (CT)v[u];
+      }
+    }
+  }
+
+  CT acc[P2];
+#pragma unroll
+  for (int q = 0; q < P2; ++q) acc[q] = (CT)0;
+
+  // x and y: lines inside the plane, lane-local
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int S1 = k == 0 ? 1 : N1;
+    const CT a = (CT)(vel.u[k] * g.scale[k]);
+    CT lown[N1], lext[N1], Gin[N1];
+#pragma unroll
+    for (int bb = 0; bb < N1; ++bb) {
+      const CT lL = (CT)sreg(A.op.lamL[bb]), lR = (CT)sreg(A.op.lamR[bb]);
+      const CT gL = (CT)sreg(A.op.GL[bb]), gR = (CT)sreg(A.op.GR[bb]);
+      lown[bb] = pos[k] ? lL : lR;
+      lext[bb] = use_right[k] ? lR : lL;
+      Gin[bb] = pos[k] ? gL : gR;
+    }
+#pragma unroll
+    for (int base = 0; base < P2; ++base) {
+      if ((base / S1) % N1 != 0) continue;
+      CT line[N1];
+#pragma unroll
+      for (int bb = 0; bb < N1; ++bb) line[bb] = f[base + bb * S1];
+      CT own = (CT)0, ext = (CT)0;
+#pragma unroll
+      for (int bb = 0; bb < N1; ++bb) {
+        own += lown[bb] * line[bb];
+        ext += lext[bb] * nb[k][base + bb * S1];
+      }
+      const CT jump = a * (ext - own);
+#pragma unroll
+      for (int ia = 0; ia < N1; ++ia) {
+        CT df = (CT)0;
+#pragma unroll
+        for (int bb = 0; bb < N1; ++bb) df += (CT)sreg(A.op.D[ia][bb]) * line[bb];
+        acc[base + ia * S1] += a * df + jump * Gin[ia];
+      }
+    }
+  }
+  // z: the column of node q is spread over the group's lanes
+  {
+    const CT a = (CT)(vel.u[2] * g.scale[2]);
+    CT lown[N1], Drow[N1];
+    CT lext_mine = (CT)0, gin_mine = (CT)0;
+#pragma unroll
+    for (int bb = 0; bb < N1; ++bb) {
+      const CT lL = (CT)sreg(A.op.lamL[bb]), lR = (CT)sreg(A.op.lamR[bb]);
+      lown[bb] = pos[2] ? lL : lR;
+      const CT le = use_right[2] ? lR : lL;
+      const CT gl = pos[2] ? (CT)sreg(A.op.GL[bb]) : (CT)sreg(A.op.GR[bb]);
+      lext_mine = bb == lp ? le : lext_mine;
+      gin_mine = bb == lp ? gl : gin_mine;
+      CT dr = (CT)0;
+#pragma unroll
+      for (int ia = 0; ia < N1; ++ia) dr = ia == lp ? (CT)sreg(A.op.D[ia][bb]) : dr;
+      Drow[bb] = dr;
+    }
+    if (!live) lext_mine = (CT)0;
+#pragma unroll
+    for (int q = 0; q < P2; ++q) {
+      CT col[N1];
+      col[0] = group_bcast<G, 0>(f[q]);
+      if constexpr (N1 > 1) col[1] = group_bcast<G, 1>(f[q]);
+      if constexpr (N1 > 2) col[2] = group_bcast<G, 2>(f[q]);
+      if constexpr (N1 > 3) col[3] = group_bcast<G, 3>(f[q]);
+      CT own = (CT)0, df = (CT)0;
+#pragma unroll
+      for (int bb = 0; bb < N1; ++bb) {
+        own += lown[bb] * col[bb];
+        df += Drow[bb] * col[bb];
+      }
+      const CT ext = group_allsum<G>(lext_mine * nb[2][q]);
+      acc[q] += a * df + a * (ext - own) * gin_mine;
+    }
+  }
+
+  if (A.collide) __syncthreads();
+  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
+  CT L[P2];
+#pragma unroll
+  for (int q = 0; q < P2; ++q) {
+    CT c = (CT)0;
+    if (A.collide) {
+      const int i = pl * P2 + q;
+      const CT* ti = tab + i * S;
+      const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
+      c = (gq - f[q]) * itau[i];
+    }
+    L[q] = -acc[q] + c;
+  }
+
+  if constexpr (MODE == 1) {
+    double* out = (double*)A.out;
+    if (act) {
+      double* oe = out + ((e - A.out_e0) * NS + pl * P2) * nv + j;
+#pragma unroll
+      for (int q = 0; q < P2; ++q) oe[(int64_t)q * nv] = (double)L[q];
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
+  } else {
+    const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
+    CT o[P2];
+    if (A.a != 0.0) {
+#pragma unroll
+      for (int q = 0; q < P2; ++q) o[q] = ca * fnv[q] + cb * (f[q] + dt * L[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < P2; ++q) o[q] = cb * (f[q] + dt * L[q]);
+    }
+    if (A.limiter) {
+      // element mean and minimum over all planes of the velocity
+      CT part = (CT)0;
+      CT fmin = o[0];
+#pragma unroll
+      for (int q = 0; q < P2; ++q) {
+        CT wq = (CT)0;  // Gauss weight of node q of this lane's plane
+#pragma unroll
+        for (int bb = 0; bb < N1; ++bb) wq = bb == lp ? (CT)sreg(A.op.W[bb * P2 + q]) : wq;
+        part += wq * o[q];
+        fmin = o[q] < fmin ? o[q] : fmin;
+      }
+      if (!live) {
+        part = (CT)0;
+        fmin = (CT)INFINITY;
+      }
+      const CT mean = group_allsum<G>(part) / (CT)A.op.Wsum;
+      fmin = group_allmin<G>(fmin);
+      const bool hit = valid && (fmin < (CT)0);
+      if (hit && mean != fmin) {
+        CT beta = fabs(mean / (mean - fmin));
+        beta = beta > (CT)1 ? (CT)1 : beta;
+#pragma unroll
+        for (int q = 0; q < P2; ++q) o[q] = mean + beta * (o[q] - mean);
+      }
+      const unsigned long long nh = __popcll(__ballot(hit && lp == 0));
+      const unsigned long long nb2 = __popcll(__ballot(hit && lp == 0 && !(mean > (CT)0)));
+      if ((threadIdx.x & 63) == 0 && nh) {
+        atomicAdd(&A.diag[2], nh);
+        if (nb2) atomicAdd(&A.diag[3], nb2);
+      }
+    }
+    if (act) {
+      ST* oe = (ST*)A.out + (node0 + pl * P2) * nv + j;
+#pragma unroll
+      for (int q = 0; q < P2; ++q) oe[(int64_t)q * nv] = (ST)o[q];
+    }
+    plane_partials<P, CT>(o, vel, A.partials, node0, g.nchunk, chunk, lp, red);
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
+  }
+}
+
+template <int P, typename ST>
+__global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
+  using CT = typename Compute<ST>::T;
+  using PL = Plane3<P>;
+  constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
+  __shared__ double red[PlaneRed<P>::LDS];
+  const DevGeom& g = A.g;
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = (int)(w / A.ecount);
+  const int64_t e = A.e0 + (w % A.ecount);
+  const int64_t nv = g.nv;
+  const int lp = (int)threadIdx.x % G;
+  const bool live = lp < N1;
+  const int pl = live ? lp : N1 - 1;
+  const int j = chunk * VB + (int)threadIdx.x / G;
+  const bool valid = j < nv;
+  const int jj = valid ? j : (int)nv - 1;
+  Vel vel = velocity_of(g, jj);
+  if (!(valid && live)) vel.w = 0.0;
+  const ST* fe = (const ST*)A.fin + (e * NS + pl * P2) * nv + jj;
+  CT f[P2];
+#pragma unroll
+  for (int q = 0; q < P2; ++q) f[q] = (CT)fe[(int64_t)q * nv];
+  plane_partials<P, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, lp, red);
+}
+
+}  // namespace bgk

@@ -5,6 +5,7 @@
 // solve for the discretely conservative equilibrium, and state conversion /
 // Maxwellian initialisation. All launched on the caller's stream.
 #include "bgk_device.hpp"
+#include "bgk_device3d.hpp"
 #include "bgk_launch.hpp"
 
 namespace bgk {
@@ -323,15 +324,30 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
     else                                                                   \
       hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, 0, s, A);     \
     break;
+#define BGK_CASE3(P)                                                       \
+  case 30 + P:                                                             \
+    if (mode == 0)                                                         \
+      hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds, s, A);    \
+    else if (mode == 1)                                                    \
+      hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds, s, A);    \
+    else                                                                   \
+      hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, 0, s, A);       \
+    break;
   switch (key) {
     BGK_CASE(1, 1) BGK_CASE(1, 2) BGK_CASE(1, 3)
     BGK_CASE(2, 1) BGK_CASE(2, 2) BGK_CASE(2, 3)
-    BGK_CASE(3, 1) BGK_CASE(3, 2) BGK_CASE(3, 3)
+    BGK_CASE3(1) BGK_CASE3(2) BGK_CASE3(3)
     default:
       return hipErrorInvalidValue;
   }
 #undef BGK_CASE
+#undef BGK_CASE3
   return hipGetLastError();
+}
+
+int velocities_per_block(int dim, int order) {
+  if (dim < 3) return kBlock;
+  return order + 1 <= 2 ? Plane3<1>::VB : Plane3<3>::VB;
 }
 
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s) {

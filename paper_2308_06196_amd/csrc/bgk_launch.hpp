@@ -11,6 +11,10 @@
 
 namespace bgk {
 
+// Velocities covered by one work-group of the stage kernel (the moment
+// partials are per such chunk).
+int velocities_per_block(int dim, int order);
+
 // mode 0: fused RK stage; 1: residual L(f) in FP64; 2: moment partials only.
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s);
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s);

@@ -216,7 +216,8 @@ Layout layout_of(const bgk_problem* pb) {
   for (int k = 0; k < pb->dim; ++k) L.ns *= pb->order + 1;
   L.nx = L.ne * L.ns;
   L.nv = (int64_t)pb->nvel[0] * pb->nvel[1] * pb->nvel[2];
-  L.nchunk = (int)((L.nv + kBlock - 1) / kBlock);
+  const int vb = velocities_per_block(pb->dim, pb->order);
+  L.nchunk = (int)((L.nv + vb - 1) / vb);
   const size_t s = pb->precision == BGK_FP64 ? 8 : 4;
   L.fbytes = (size_t)L.nx * (size_t)L.nv * s;
   size_t off = 0;
