@@ -8,11 +8,13 @@
 //                        one entry per 256-wide velocity chunk
 //   params[node][8]      FP64 (alpha_0..alpha_4, 1/tau, tau, status) of the
 //                        discretely conservative equilibrium
-//   etab[node][S]        FP64 one-dimensional factors of that equilibrium,
-//                        S = nv1[0] + nv1[1] + nv1[2]:
+//   etab[node][S]        one-dimensional factors of that equilibrium and
+//                        1/tau, in the storage precision of f,
+//                        S = nv1[0] + nv1[1] + nv1[2] + 1:
 //                        g(u) = Ex[bx] Ey[by] Ez[bz] with
 //                        Ex[b] = exp(alpha_0 + alpha_1 u_b + alpha_4 u_b^2/2),
-//                        Ey[b] = exp(alpha_2 u_b + alpha_4 u_b^2/2), Ez alike
+//                        Ey[b] = exp(alpha_2 u_b + alpha_4 u_b^2/2), Ez alike;
+//                        the last entry of a row is 1/tau of the node
 //
 // Thread mapping of the stage kernel: one work-group = one element x one
 // chunk of 256 consecutive velocities; one lane = one velocity j and all
@@ -38,7 +40,7 @@ struct DevGeom {
   int32_t nelem[3];
   int32_t bc[3][2];
   int32_t nv1[3];
-  int32_t tabw;  // S = nv1[0] + nv1[1] + nv1[2]
+  int32_t tabw;  // S = nv1[0] + nv1[1] + nv1[2] + 1 (factors, then 1/tau)
   int64_t ne, nx, nv;
   int32_t nchunk;
   double vlo[3], du[3];
@@ -60,7 +62,8 @@ struct StageArgs {
   const void* fn;   // f^n (storage precision), read when a != 0
   void* out;        // stage output (storage precision), or FP64 residual
   const double* params;
-  const double* etab;
+  const void* etab;      // equilibrium factors, storage precision
+  const int32_t* order;  // traversal order of the elements (null: lexicographic)
   double* partials;
   unsigned long long* diag;  // newton it max, newton fail, lim hits, lim bad, stages
   double dt, a, b;
@@ -72,11 +75,11 @@ struct NewtonArgs {
   DevGeom g;
   const double* partials;
   double* params;
-  double* etab;
-  double* Q;  // optional [nx][5] output of the reduced moments
+  void* etab;  // equilibrium factors, written in the storage precision
+  double* Q;   // optional [nx][5] output of the reduced moments
   unsigned long long* diag;
   double gamma, mu_ref, theta_ref, omega, tol;
-  int32_t maxit, collide;
+  int32_t maxit, collide, etab_f32;
 };
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
@@ -88,6 +91,15 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   const int64_t x = bid % kNumXCD, k = bid / kNumXCD;
   const int64_t per = nb / kNumXCD, rem = nb % kNumXCD;
   return x * per + (x < rem ? x : rem) + k;
+}
+
+// Element of work item w (velocity-chunk major): the k-th element of the
+// traversal order, which visits hexahedra brick by brick so that the
+// upwind neighbours of an element were visited a few work items earlier.
+__device__ __forceinline__ int64_t work_element(const int32_t* order, int64_t e0, int64_t w,
+                                                int64_t ecount) {
+  const int64_t k = w % ecount;
+  return order ? (int64_t)order[k] : e0 + k;
 }
 
 // ---------------------------------------------------------------------------
@@ -311,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
-  const int64_t e = A.e0 + (w % A.ecount);
+  const int64_t e = work_element(A.order, A.e0, w, A.ecount);
   const int64_t nv = g.nv;
   const int S = g.tabw;
   const int64_t node0 = e * NS;
@@ -366,21 +378,20 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     src[k] = fin + src_e * NS * nv + src_j;
   }
 
-  // Issue the global loads before any use: the element's equilibrium
-  // factors and 1/tau (first batch), own nodes, f^n, the upwind neighbours'
-  // nodes.
+  // Issue the global loads before any use: the element's equilibrium rows
+  // (factors and 1/tau, first batch), own nodes, f^n, the upwind neighbours'
+  // nodes. Every lane loads (clamped index, no branch): a conditional load
+  // makes the compiler wait for it right there, ahead of the bulk loads.
   constexpr int kU = 8;
   const int ntab = NS * S;
-  const double* et = A.etab + node0 * S;
-  double tv[kU];
-  double itv = 0.0;
+  const ST* et = (const ST*)A.etab + node0 * S;
+  ST tv[kU];
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
-      tv[u] = t < ntab ? et[t] : 0.0;
+      tv[u] = et[t < ntab ? t : ntab - 1];
     }
-    if (threadIdx.x < NS) itv = A.params[(node0 + threadIdx.x) * 8 + 5];
   }
   const ST* fe = fin + node0 * nv + jj;
   CT f[NS];
@@ -401,22 +412,20 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][(int64_t)i * nv];
   }
-  // equilibrium factors (NS x S) and 1/tau (NS) of this element -> LDS
-  CT* itau = tab + NS * S;
+  // equilibrium rows (NS x S) of this element -> LDS
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
       if (t < ntab) tab[t] = (CT)tv[u];
     }
-    if (threadIdx.x < NS) itau[threadIdx.x] = (CT)itv;
     // factors beyond the first batch (large velocity grids or 3-D elements)
     for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
-      double v[kU];
+      ST v[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int t = t0 + u * kBlock + (int)threadIdx.x;
-        v[u] = t < ntab ? et[t] : 0.0;
+        v[u] = et[t < ntab ? t : ntab - 1];
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
@@ -484,7 +493,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     if (A.collide) {
       const CT* ti = tab + i * S;
       const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
-      c = (gq - f[i]) * itau[i];
+      c = (gq - f[i]) * ti[S - 1];
     }
     L[i] = -acc[i] + c;
   }
@@ -552,7 +561,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
-  const int64_t e = A.e0 + (w % A.ecount);
+  const int64_t e = work_element(A.order, A.e0, w, A.ecount);
   const int64_t nv = g.nv;
   const int j = chunk * kBlock + (int)threadIdx.x;
   const bool valid = j < nv;

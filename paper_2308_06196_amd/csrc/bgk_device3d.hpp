@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
-  const int64_t e = A.e0 + (w % A.ecount);
+  const int64_t e = work_element(A.order, A.e0, w, A.ecount);
   const int64_t nv = g.nv;
   const int S = g.tabw;
   const int64_t node0 = e * NS;
@@ -225,16 +225,14 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
   // plane, the x-, y- and z-neighbours' planes
   constexpr int kU = 8;
   const int ntab = NS * S;
-  const double* et = A.etab + node0 * S;
-  double tv[kU];
-  double itv = 0.0;
+  const ST* et = (const ST*)A.etab + node0 * S;
+  ST tv[kU];
   if (A.collide) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kU; ++u) {  // clamped, unconditional loads
       const int t = u * kBlock + (int)threadIdx.x;
-      tv[u] = t < ntab ? et[t] : 0.0;
+      tv[u] = et[t < ntab ? t : ntab - 1];
     }
-    if (threadIdx.x < NS) itv = A.params[(node0 + threadIdx.x) * 8 + 5];
   }
   const ST* fe = fin + (node0 + pl * P2) * nv + jj;
   CT f[P2];
@@ -254,20 +252,18 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
 #pragma unroll
     for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][(int64_t)q * nv];
 
-  CT* itau = tab + NS * S;
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
       if (t < ntab) tab[t] = (CT)tv[u];
     }
-    if (threadIdx.x < NS) itau[threadIdx.x] = (CT)itv;
     for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
-      double v[kU];
+      ST v[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int t = t0 + u * kBlock + (int)threadIdx.x;
-        v[u] = t < ntab ? et[t] : 0.0;
+        v[u] = et[t < ntab ? t : ntab - 1];
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
@@ -364,7 +360,7 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
       const int i = pl * P2 + q;
       const CT* ti = tab + i * S;
       const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
-      c = (gq - f[q]) * itau[i];
+      c = (gq - f[q]) * ti[S - 1];
     }
     L[q] = -acc[q] + c;
   }
@@ -438,7 +434,7 @@ __global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
-  const int64_t e = A.e0 + (w % A.ecount);
+  const int64_t e = work_element(A.order, A.e0, w, A.ecount);
   const int64_t nv = g.nv;
   const int lp = (int)threadIdx.x % G;
   const bool live = lp < N1;

@@ -60,22 +60,27 @@ __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
   return 0;
 }
 
-// All-reduce of one FP64 value over the 16 lanes of a team (one DPP row):
-// partners lane ^ 8, the mirror inside 8 lanes, lane ^ 2, lane ^ 1. Each
-// step pairs lanes symmetrically, so every lane ends with the same bits.
+// All-reduce of one FP64 value over the T lanes of a team (T = 16: one DPP
+// row, partners lane ^ 8, the mirror inside 8 lanes, lane ^ 2, lane ^ 1;
+// T = 4: one quad). Each step pairs lanes symmetrically, so every lane ends
+// with the same bits.
+template <int T>
 __device__ __forceinline__ double team_sum(double x) {
-  x += dpp_partner<8>(x);
-  x += dpp_partner<4>(x);
+  if constexpr (T == 16) {
+    x += dpp_partner<8>(x);
+    x += dpp_partner<4>(x);
+  }
   x += dpp_partner<2>(x);
   x += dpp_partner<1>(x);
   return x;
 }
 
-// One 16-lane team per spatial node. The lanes split the velocity chunks of
-// the moment partials and the nodes of each one-dimensional sum; the 5x5
-// solve is repeated identically in every lane of the team.
-constexpr int kTeam = 16;
-
+// One team of kTeam lanes per spatial node. The lanes split the velocity
+// chunks of the moment partials and the nodes of each one-dimensional sum;
+// the 5x5 solve is repeated identically in every lane of the team. Large
+// meshes use 4-lane teams (less redundant solve work), small ones 16-lane
+// teams (enough waves to fill the device).
+template <int kTeam>
 __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   const DevGeom& g = A.g;
   const int64_t node_raw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kTeam;
@@ -101,7 +106,7 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
       for (int m = 0; m < 5; ++m) Q[m] += v[u][m];
   }
 #pragma unroll
-  for (int m = 0; m < 5; ++m) Q[m] = team_sum(Q[m]);
+  for (int m = 0; m < 5; ++m) Q[m] = team_sum<kTeam>(Q[m]);
   if (A.Q && r == 0 && active) {
 #pragma unroll
     for (int m = 0; m < 5; ++m) A.Q[node * 5 + m] = Q[m];
@@ -151,7 +156,7 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
           S[c][4] += t * u2 * u2;
         }
 #pragma unroll
-        for (int n = 0; n < 5; ++n) S[c][n] = team_sum(S[c][n]);
+        for (int n = 0; n < 5; ++n) S[c][n] = team_sum<kTeam>(S[c][n]);
       }
       double m[3][5];
 #pragma unroll
@@ -228,8 +233,8 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
 #pragma unroll
     for (int a = 0; a < 5; ++a) al[a] = __builtin_nan("");
   }
-  // one-dimensional factors of the equilibrium, exp(alpha_0) folded into x
-  double* et = A.etab + node * g.tabw;
+  // one-dimensional factors of the equilibrium, exp(alpha_0) folded into x,
+  // stored in the storage precision of f
   int off = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -238,7 +243,11 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
     if (active) {
       for (int b = r; b < N; b += kTeam) {
         const double u = g.vlo[c] + b * g.du[c];
-        et[off + b] = exp(a0 + al[1 + c] * u + al[4] * (0.5 * u * u));
+        const double v = exp(a0 + al[1 + c] * u + al[4] * (0.5 * u * u));
+        if (A.etab_f32)
+          ((float*)A.etab)[node * g.tabw + off + b] = (float)v;
+        else
+          ((double*)A.etab)[node * g.tabw + off + b] = v;
       }
     }
     off += N;
@@ -251,11 +260,15 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
     out[5] = 1.0 / tau;
     out[6] = tau;
     out[7] = (double)status;
+    // 1/tau closes the node's row of the factor table
+    if (A.etab_f32)
+      ((float*)A.etab)[node * g.tabw + off] = (float)(1.0 / tau);
+    else
+      ((double*)A.etab)[node * g.tabw + off] = 1.0 / tau;
   }
   // counters: one atomic per wave (the four teams of a wave reduced first)
   int itw = active ? iters : 0;
-  itw = max(itw, __shfl_xor(itw, 16, 64));
-  itw = max(itw, __shfl_xor(itw, 32, 64));
+  for (int o = kTeam; o < 64; o <<= 1) itw = max(itw, __shfl_xor(itw, o, 64));
   const unsigned long long nfail = __popcll(__ballot(active && r == 0 && status != 0));
   if ((threadIdx.x & 63) == 0) {
     if (itw > 0) atomicMax(&A.diag[0], (unsigned long long)itw);
@@ -314,7 +327,7 @@ template <typename ST>
 static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   const dim3 grid((unsigned)(A.g.nchunk * A.ecount)), block(kBlock);
   const int key = A.g.dim * 10 + (A.g.n1 - 1);
-  const size_t lds = A.collide ? (size_t)A.g.ns * (A.g.tabw + 1) * sizeof(ST) : 0;
+  const size_t lds = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(ST) : 0;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
     if (mode == 0)                                                         \
@@ -356,7 +369,10 @@ hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t
 }
 
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_newton, dim3(grid_of(A.g.nx * kTeam, 256)), dim3(256), 0, s, A);
+  if (A.g.nx >= 65536)
+    hipLaunchKernelGGL(k_newton<4>, dim3(grid_of(A.g.nx * 4, 256)), dim3(256), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_newton<16>, dim3(grid_of(A.g.nx * 16, 256)), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 

@@ -163,7 +163,7 @@ void gauss_nodes(int n1, double* xi) {
 }
 
 struct Layout {
-  size_t f[3], partials, params, etab, Q, prim, diag, total;
+  size_t f[3], partials, params, etab, order, Q, prim, diag, total;
   int64_t nx, nv, ne;
   int ns, nchunk;
   size_t fbytes;
@@ -230,7 +230,10 @@ Layout layout_of(const bgk_problem* pb) {
   L.params = off;
   off = align_up(off + (size_t)L.nx * 8 * sizeof(double));
   L.etab = off;
-  off = align_up(off + (size_t)L.nx * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2]) * sizeof(double));
+  off = align_up(off + (size_t)L.nx * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1) *
+                             sizeof(double));
+  L.order = off;
+  off = align_up(off + (size_t)L.ne * sizeof(int32_t));
   L.Q = off;
   off = align_up(off + (size_t)L.nx * 5 * sizeof(double));
   L.prim = off;
@@ -267,6 +270,9 @@ struct bgk_solver {
   double* partials() const { return (double*)(ws + L.partials); }
   double* params() const { return (double*)(ws + L.params); }
   double* etab() const { return (double*)(ws + L.etab); }
+  int32_t* order() const { return (int32_t*)(ws + L.order); }
+  bool order_ready = false;
+  std::vector<int32_t> order_host;  // traversal order (empty: lexicographic)
   double* Q() const { return (double*)(ws + L.Q); }
   double* prim() const { return (double*)(ws + L.prim); }
   unsigned long long* diag() const { return (unsigned long long*)(ws + L.diag); }
@@ -282,6 +288,7 @@ StageArgs stage_args(const bgk_solver* s) {
   A.op = s->op;
   A.params = s->params();
   A.etab = s->etab();
+  A.order = s->order_host.empty() ? nullptr : s->order();
   A.partials = s->partials();
   A.diag = s->diag();
   A.e0 = 0;
@@ -308,17 +315,43 @@ NewtonArgs newton_args(const bgk_solver* s) {
   N.tol = s->pb.newton_tol > 0.0 ? s->pb.newton_tol : 1e-14;
   N.maxit = s->pb.newton_maxit > 0 ? s->pb.newton_maxit : 20;
   N.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
+  N.etab_f32 = s->precision == BGK_FP32 ? 1 : 0;
   return N;
 }
 
-// The device counters are cleared by the first call that queues device work
-// (create itself never touches the workspace).
+// The device counters are cleared, and the element traversal order is
+// uploaded, by the first call that queues device work (create itself never
+// touches the workspace).
 bgk_status ensure_counters(bgk_solver* s) {
   if (!s->counters_ready) {
     HIP_TRY(hipMemsetAsync(s->diag(), 0, 8 * sizeof(unsigned long long), s->stream));
     s->counters_ready = true;
   }
+  if (!s->order_ready) {
+    if (!s->order_host.empty()) {
+      HIP_TRY(hipMemcpyAsync(s->order(), s->order_host.data(),
+                             s->order_host.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             s->stream));
+    }
+    s->order_ready = true;
+  }
   return BGK_OK;
+}
+
+// Brick traversal of a hexahedral mesh: bricks of 4 x 4 x 4 elements
+// (clipped at the mesh boundary) in lexicographic brick order, elements
+// lexicographic inside a brick.
+void brick_order(const int32_t* ne, std::vector<int32_t>& out) {
+  const int B = 4;
+  out.clear();
+  out.reserve((size_t)ne[0] * ne[1] * ne[2]);
+  for (int bz = 0; bz < ne[2]; bz += B)
+    for (int by = 0; by < ne[1]; by += B)
+      for (int bx = 0; bx < ne[0]; bx += B)
+        for (int z = bz; z < std::min(bz + B, ne[2]); ++z)
+          for (int y = by; y < std::min(by + B, ne[1]); ++y)
+            for (int x = bx; x < std::min(bx + B, ne[0]); ++x)
+              out.push_back(x + ne[0] * (y + ne[1] * z));
 }
 
 bgk_status moments_of(bgk_solver* s, const void* fstore) {
@@ -401,6 +434,10 @@ bgk_status mark(bgk_solver* s) {
 bgk_status reset_state_flags(bgk_solver* s) {
   HIP_TRY(hipMemsetAsync(s->diag(), 0, 8 * sizeof(unsigned long long), s->stream));
   s->counters_ready = true;
+  {
+    bgk_status st = ensure_counters(s);
+    if (st) return st;
+  }
   s->failed = false;
   s->has_state = true;
   s->partials_valid = false;
@@ -474,12 +511,13 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
     g.vlo[k] = pb->vlo[k];
     g.du[k] = (pb->vhi[k] - pb->vlo[k]) / (pb->nvel[k] - 1);
   }
-  g.tabw = pb->nvel[0] + pb->nvel[1] + pb->nvel[2];
+  g.tabw = pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1;
   g.ne = s->L.ne;
   g.nx = s->L.nx;
   g.nv = s->L.nv;
   g.nchunk = s->L.nchunk;
   build_ops(g.n1, g.dim, s->op);
+  if (pb->dim == 3) brick_order(g.nelem, s->order_host);
   *out = s;
   return BGK_OK;
 }
@@ -634,6 +672,7 @@ bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_
   if (cap < 1)
     return fail(BGK_ERR_UNSUPPORTED, "host residual with FP32 storage needs >= 2 elements; "
                 "use device buffers");
+  A.order = nullptr;  // element ranges: lexicographic
   for (int64_t e0 = 0; e0 < s->L.ne; e0 += cap) {
     A.e0 = e0;
     A.ecount = std::min(cap, s->L.ne - e0);

@@ -293,3 +293,18 @@ def test_mach2_reduced_fp32_and_fp64(torch):
         s.rk3_step(dt, 2)
         assert rel_max(s.get_state().cpu().numpy(), f_orc) < tol, prec
         s.diagnostics()
+
+
+def test_large_mesh_one_step(torch):
+    """A 16^3-element hexahedral mesh (262,144 nodes: the large-mesh Newton teams and
+    the brick traversal) with a small velocity grid, one step vs the oracle."""
+    pb = wl.tgv3d(n=16, order=3, nv1=4)
+    _say("large-mesh", pb["nelem"], pb["nvel"])
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "tgv3d", seed=9, amp=0.1)
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb)
+    s.set_state(dev(torch, f0))
+    s.rk3_step(dt, 1)
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 1)
+    assert rel_max(s.get_state().cpu().numpy(), f_orc) < 1e-12
