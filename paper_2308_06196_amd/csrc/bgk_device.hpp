@@ -245,6 +245,16 @@ __device__ __forceinline__ Vel velocity_of(const DevGeom& g, int j) {
 // Uniform kernel-argument value as an opaque scalar register value: a
 // per-lane select between two of them then stays a register select (the
 // compiler would otherwise turn it into a load through a selected address).
+// Work-group barrier that orders LDS only. A plain __syncthreads() also
+// orders global memory, so it waits for every load and store in flight (the
+// bulk loads issued ahead of the table stores, the output stores ahead of the
+// reduction); this one waits for LDS operations alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ double sreg(double x) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
@@ -292,7 +302,7 @@ __device__ __forceinline__ void element_partials(const CT (&fv)[NS], const Vel& 
     for (int q = M; q < MP; ++q) v[q] = 0.0;
     wave_level<MP, 0>(v, red + (wave * NG + gi) * MP, lane, 0, 0);
   }
-  __syncthreads();
+  lds_barrier();
   for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
     const int gi = t / M, idx = t - gi * M;
     double s = red[gi * MP + idx];
@@ -302,11 +312,31 @@ __device__ __forceinline__ void element_partials(const CT (&fv)[NS], const Vel& 
   }
 }
 
+// Equilibrium rows from index kU * kBlock on (the first kU * kBlock entries
+// are loaded with the bulk loads) -> LDS.
+template <int kU, typename ST, typename CT>
+__device__ __forceinline__ void table_rest(CT* tab, const ST* et, int ntab) {
+  for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
+    ST v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * kBlock + (int)threadIdx.x;
+      v[u] = et[t < ntab ? t : ntab - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * kBlock + (int)threadIdx.x;
+      if (t < ntab) tab[t] = (CT)v[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stage kernel: FR transport (volume + upwind inflow-face lift) + BGK
 // relaxation + SSP-RK combine + positivity limiter + next-stage moment
-// partials (MODE 0), or the plain residual L(f) in FP64 (MODE 1).
-// Dynamic LDS: NS * S + NS values of type CT (equilibrium factors, 1/tau).
+// partials (MODE 0: a stage that combines with f^n; MODE 3: the first stage,
+// a = 0, which does not read f^n), or the plain residual L(f) in FP64
+// (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
 // ---------------------------------------------------------------------------
 template <int DIM, int P, typename ST, int MODE>
 __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
@@ -379,8 +409,8 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   }
 
   // Issue the global loads before any use: the element's equilibrium rows
-  // (factors and 1/tau, first batch), own nodes, f^n, the upwind neighbours'
-  // nodes. Every lane loads (clamped index, no branch): a conditional load
+  // (factors and 1/tau, first batch), own nodes, the upwind neighbours'
+  // nodes, f^n. Every lane loads (clamped index, no branch): a conditional load
   // makes the compiler wait for it right there, ahead of the bulk loads.
   constexpr int kU = 8;
   const int ntab = NS * S;
@@ -397,14 +427,6 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   CT f[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
-  CT fnv[NS];
-  if constexpr (MODE == 0) {
-    if (A.a != 0.0) {
-      const ST* fn = (const ST*)A.fn + node0 * nv + jj;
-#pragma unroll
-      for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[(int64_t)i * nv];
-    }
-  }
   CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
   if constexpr (kPreload) {
 #pragma unroll
@@ -412,26 +434,20 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][(int64_t)i * nv];
   }
+  // f^n last: it is needed only by the final combine, so the transport can
+  // start while it is still in flight
+  CT fnv[NS];
+  if constexpr (MODE == 0) {
+    const ST* fn = (const ST*)A.fn + node0 * nv + jj;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[(int64_t)i * nv];
+  }
   // equilibrium rows (NS x S) of this element -> LDS
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
       if (t < ntab) tab[t] = (CT)tv[u];
-    }
-    // factors beyond the first batch (large velocity grids or 3-D elements)
-    for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
-      ST v[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int t = t0 + u * kBlock + (int)threadIdx.x;
-        v[u] = et[t < ntab ? t : ntab - 1];
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int t = t0 + u * kBlock + (int)threadIdx.x;
-        if (t < ntab) tab[t] = (CT)v[u];
-      }
     }
   }
 
@@ -484,18 +500,22 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
 
   // BGK relaxation towards the discretely conservative equilibrium,
   // g = Ex[bx] Ey[by] Ez[bz] from the LDS factors
-  if (A.collide) __syncthreads();
-  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
   CT L[NS];
+  if (A.collide) {  // uniform; one branch, so the LDS reads of all nodes overlap
+    // rows beyond the first batch (large velocity grids); loaded only now so
+    // that their loop does not hold back the waits of the bulk loads
+    table_rest<kU>(tab, et, ntab);
+    lds_barrier();
+    const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    CT c = (CT)0;
-    if (A.collide) {
+    for (int i = 0; i < NS; ++i) {
       const CT* ti = tab + i * S;
       const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
-      c = (gq - f[i]) * ti[S - 1];
+      L[i] = -acc[i] + (gq - f[i]) * ti[S - 1];
     }
-    L[i] = -acc[i] + c;
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) L[i] = -acc[i];
   }
 
   if constexpr (MODE == 1) {
@@ -509,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   } else {
     const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
     CT o[NS];
-    if (A.a != 0.0) {
+    if constexpr (MODE == 0) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) o[i] = ca * fnv[i] + cb * (f[i] + dt * L[i]);
     } else {

@@ -137,7 +137,7 @@ __device__ __forceinline__ void plane_partials(const CT (&fv)[Plane3<P>::P2], co
     for (int q = M; q < MP; ++q) v[q] = 0.0;
     wave_level_hi<MP, 0, MP>(v, red + (wave * NGR + gi) * 8 * MP, lane, 0);
   }
-  __syncthreads();
+  lds_barrier();
   // final sums: for each plane, node of the plane and moment, add the
   // 4 waves x (8 / G) low-lane slots that hold that plane
   constexpr int NOUT = PL::N1 * P2 * 5;
@@ -221,9 +221,9 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
     src[k] = fin + (src_e * NS + pl * P2) * nv + src_j;
   }
 
-  // loads: equilibrium factors and 1/tau (first batch), own plane, f^n
-  // plane, the x-, y- and z-neighbours' planes
-  constexpr int kU = 8;
+  // loads: equilibrium rows (first batch), own plane, the x-, y- and
+  // z-neighbours' planes, f^n plane
+  constexpr int kU = P == 3 ? 16 : 8;  // first batch: 16^3 grids at p = 3
   const int ntab = NS * S;
   const ST* et = (const ST*)A.etab + node0 * S;
   ST tv[kU];
@@ -238,38 +238,23 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
   CT f[P2];
 #pragma unroll
   for (int q = 0; q < P2; ++q) f[q] = (CT)fe[(int64_t)q * nv];
-  CT fnv[P2];
-  if constexpr (MODE == 0) {
-    if (A.a != 0.0) {
-      const ST* fn = (const ST*)A.fn + (node0 + pl * P2) * nv + jj;
-#pragma unroll
-      for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[(int64_t)q * nv];
-    }
-  }
   CT nb[3][P2];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][(int64_t)q * nv];
+  CT fnv[P2];  // last: needed only by the final combine
+  if constexpr (MODE == 0) {
+    const ST* fn = (const ST*)A.fn + (node0 + pl * P2) * nv + jj;
+#pragma unroll
+    for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[(int64_t)q * nv];
+  }
 
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
       if (t < ntab) tab[t] = (CT)tv[u];
-    }
-    for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
-      ST v[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int t = t0 + u * kBlock + (int)threadIdx.x;
-        v[u] = et[t < ntab ? t : ntab - 1];
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int t = t0 + u * kBlock + (int)threadIdx.x;
-        if (t < ntab) tab[t] = (CT)v[u];
-      }
     }
   }
 
@@ -350,19 +335,20 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
     }
   }
 
-  if (A.collide) __syncthreads();
-  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
   CT L[P2];
+  if (A.collide) {  // uniform; one branch, so the LDS reads of all nodes overlap
+    table_rest<kU>(tab, et, ntab);  // rows beyond the first batch
+    lds_barrier();
+    const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
 #pragma unroll
-  for (int q = 0; q < P2; ++q) {
-    CT c = (CT)0;
-    if (A.collide) {
-      const int i = pl * P2 + q;
-      const CT* ti = tab + i * S;
+    for (int q = 0; q < P2; ++q) {
+      const CT* ti = tab + (pl * P2 + q) * S;
       const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
-      c = (gq - f[q]) * ti[S - 1];
+      L[q] = -acc[q] + (gq - f[q]) * ti[S - 1];
     }
-    L[q] = -acc[q] + c;
+  } else {
+#pragma unroll
+    for (int q = 0; q < P2; ++q) L[q] = -acc[q];
   }
 
   if constexpr (MODE == 1) {
@@ -376,7 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
   } else {
     const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
     CT o[P2];
-    if (A.a != 0.0) {
+    if constexpr (MODE == 0) {
 #pragma unroll
       for (int q = 0; q < P2; ++q) o[q] = ca * fnv[q] + cb * (f[q] + dt * L[q]);
     } else {

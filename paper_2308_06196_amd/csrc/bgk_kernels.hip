@@ -330,8 +330,10 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   const size_t lds = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(ST) : 0;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
-    if (mode == 0)                                                         \
+    if (mode == 0 && A.a != 0.0)                                           \
       hipLaunchKernelGGL((k_stage<D, P, ST, 0>), grid, block, lds, s, A);  \
+    else if (mode == 0)                                                    \
+      hipLaunchKernelGGL((k_stage<D, P, ST, 3>), grid, block, lds, s, A);  \
     else if (mode == 1)                                                    \
       hipLaunchKernelGGL((k_stage<D, P, ST, 1>), grid, block, lds, s, A);  \
     else                                                                   \
@@ -339,8 +341,10 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
     break;
 #define BGK_CASE3(P)                                                       \
   case 30 + P:                                                             \
-    if (mode == 0)                                                         \
+    if (mode == 0 && A.a != 0.0)                                           \
       hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds, s, A);    \
+    else if (mode == 0)                                                    \
+      hipLaunchKernelGGL((k_stage3<P, ST, 3>), grid, block, lds, s, A);    \
     else if (mode == 1)                                                    \
       hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds, s, A);    \
     else                                                                   \

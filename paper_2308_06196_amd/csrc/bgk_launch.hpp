@@ -15,7 +15,8 @@ namespace bgk {
 // partials are per such chunk).
 int velocities_per_block(int dim, int order);
 
-// mode 0: fused RK stage; 1: residual L(f) in FP64; 2: moment partials only.
+// mode 0: fused RK stage (a variant that does not read f^n when a = 0);
+// 1: residual L(f) in FP64; 2: moment partials only.
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s);
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s);
 hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,
