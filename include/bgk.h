@@ -71,7 +71,15 @@ typedef enum {
   BGK_ERR_STATE = 7          /* solver failed earlier / no state installed */
 } bgk_status;
 
-typedef enum { BGK_BC_PERIODIC = 0, BGK_BC_SPECULAR = 1 } bgk_bc;
+typedef enum { BGK_BC_PERIODIC = 0, BGK_BC_SPECULAR = 1, BGK_BC_DIFFUSE = 2 } bgk_bc;
+
+/* Equilibrium the collision term relaxes to. CONSERVATIVE: the discrete
+ * Maxwellian exp(alpha . psi) whose trapezoid moments equal those of f
+ * (Newton, Sec. 2.1 velocity discretization). CONTINUOUS: the continuous
+ * Maxwellian at the (rho, U, theta) of f sampled at the velocity nodes, which
+ * does not conserve the discrete moments (the non-conservative model the
+ * paper compares against; no Newton solve). */
+typedef enum { BGK_EQ_CONSERVATIVE = 0, BGK_EQ_CONTINUOUS = 1 } bgk_equilibrium;
 
 /* Storage precision of f. FP64: everything in FP64. FP32: f stored and the
  * transport/relaxation/Runge-Kutta arithmetic in FP32; moments, Newton solve
@@ -97,6 +105,10 @@ typedef enum { BGK_HOST = 0, BGK_DEVICE = 1 } bgk_where;
  *   limiter          0 off, 1 Zhang-Shu positivity limiter after each stage.
  *   newton_maxit     Newton iteration cap (<= 0 selects 20).
  *   newton_tol       scaled moment-residual tolerance (<= 0 selects 1e-14).
+ *   equilibrium      bgk_equilibrium.
+ *   wall_theta[k][s], wall_vel[k][s]
+ *                    temperature and velocity of a BGK_BC_DIFFUSE wall on
+ *                    side s of axis k (ignored for other boundaries).
  */
 typedef struct {
   int32_t dim, order;
@@ -110,6 +122,9 @@ typedef struct {
   int32_t precision, limiter;
   int32_t newton_maxit;
   double newton_tol;
+  int32_t equilibrium;
+  double wall_theta[3][2];
+  double wall_vel[3][2][3];
 } bgk_problem;
 
 /* Counters accumulated on the device since the last state installation. */

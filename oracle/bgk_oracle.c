@@ -20,6 +20,9 @@
  *              discrete moments equal those of f), found by Newton's method
  *              with its closed-form Jacobian.
  *   Sec. 2.2   explicit time stepping (three-stage SSP Runge-Kutta here).
+ *   The non-conservative model the paper contrasts with the DVM equilibrium
+ *   (Sec. 2.1) relaxes to the continuous Maxwellian of (rho, U, theta)
+ *   sampled at the velocity nodes (problem field equilibrium = 1).
  *
  * Readings where the paper is silent (all shared with the HIP path through
  * the documented problem statement, never through code):
@@ -47,12 +50,15 @@ typedef struct {
   int32_t dim, order;
   int32_t nelem[3];
   double xlo[3], xhi[3];
-  int32_t bc[3][2]; /* 0 periodic, 1 specular wall */
+  int32_t bc[3][2]; /* 0 periodic, 1 specular wall, 2 diffuse wall */
   int32_t nvel[3];
   double vlo[3], vhi[3];
   double mu_ref, theta_ref, omega, gamma;
   int32_t limiter, newton_maxit;
   double newton_tol;
+  int32_t equilibrium;      /* 0 discretely conservative, 1 continuous Maxwellian */
+  double wall_theta[3][2];  /* diffuse wall temperature */
+  double wall_vel[3][2][3]; /* diffuse wall velocity */
 } orc_problem;
 
 typedef struct {
@@ -351,18 +357,13 @@ static int chol5_solve(const double J[5][5], const double* b, double* x) {
   return 0;
 }
 
-/* Discretely conservative equilibrium for one node: find alpha with
- * sum_j w_j psi_j exp(alpha . psi_j) = Q by Newton's method with the
- * closed-form Jacobian J = sum_j w_j psi_j psi_j^T exp(alpha . psi_j).
- * Returns 0 on success, 1 when not converged within maxit, 2 when Q is not
- * realizable (rho <= 0 or theta <= 0) or J loses definiteness.
- * iters = number of residual evaluations; resid = last scaled residual. */
-static int newton_node(const orc_ops* op, const double* Q, int maxit, double tol, double* alpha,
-                       int* iters, double* resid) {
-  double gm = op->gamma;
+/* Continuous Maxwellian at the (rho, U, theta) of the moments Q, written as
+ * exp(alpha . psi): alpha = (ln(rho/(2 pi theta)^{3/2}) - |U|^2/(2 theta),
+ * U/theta, -1/theta) (Sec. 2, Maxwellian; reading R1 for the exponent).
+ * Returns 2 when Q is not realizable. This is the equilibrium of the
+ * non-conservative model and the start of the Newton iteration below. */
+static int continuous_alpha(double gm, const double* Q, double* alpha) {
   double rho = Q[0];
-  *iters = 0;
-  *resid = INFINITY;
   if (!(rho > 0.0)) return 2;
   double U[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
   double UU = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
@@ -374,6 +375,21 @@ static int newton_node(const orc_ops* op, const double* Q, int maxit, double tol
   alpha[2] = U[1] / th;
   alpha[3] = U[2] / th;
   alpha[4] = -1.0 / th;
+  return 0;
+}
+
+/* Discretely conservative equilibrium for one node: find alpha with
+ * sum_j w_j psi_j exp(alpha . psi_j) = Q by Newton's method with the
+ * closed-form Jacobian J = sum_j w_j psi_j psi_j^T exp(alpha . psi_j).
+ * Returns 0 on success, 1 when not converged within maxit, 2 when Q is not
+ * realizable (rho <= 0 or theta <= 0) or J loses definiteness.
+ * iters = number of residual evaluations; resid = last scaled residual. */
+static int newton_node(const orc_ops* op, const double* Q, int maxit, double tol, double* alpha,
+                       int* iters, double* resid) {
+  *iters = 0;
+  *resid = INFINITY;
+  if (continuous_alpha(op->gamma, Q, alpha)) return 2;
+  const double rho = Q[0], th = -1.0 / alpha[4];
   double sc[5] = {rho, rho * sqrt(th), rho * sqrt(th), rho * sqrt(th), Q[4]};
   for (int it = 0;; ++it) {
     double s[5] = {0, 0, 0, 0, 0}, c[5] = {0, 0, 0, 0, 0};
@@ -443,7 +459,13 @@ static void node_collision(const orc_problem* pr, const orc_ops* op, const doubl
   double Q[5], alpha[5], tau, res;
   int its;
   node_moments(op, fj, Q);
-  int st = newton_node(op, Q, pr->newton_maxit, pr->newton_tol, alpha, &its, &res);
+  int st;
+  if (pr->equilibrium == 1) { /* non-conservative model: no Newton solve */
+    its = 0;
+    st = continuous_alpha(op->gamma, Q, alpha);
+  } else {
+    st = newton_node(op, Q, pr->newton_maxit, pr->newton_tol, alpha, &its, &res);
+  }
   if (its > dg->newton_it_max) dg->newton_it_max = its;
   if (st) dg->newton_fail += 1;
   node_tau(pr, op, Q, &tau);

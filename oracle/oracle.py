@@ -49,6 +49,9 @@ class _Problem(C.Structure):
         ("gamma", C.c_double),
         ("limiter", C.c_int32), ("newton_maxit", C.c_int32),
         ("newton_tol", C.c_double),
+        ("equilibrium", C.c_int32),
+        ("wall_theta", (C.c_double * 2) * 3),
+        ("wall_vel", ((C.c_double * 3) * 2) * 3),
     ]
 
 
@@ -64,7 +67,11 @@ class Diag(C.Structure):
 class Problem:
     """Uniform Cartesian box in d dims, nodal FR order p, 3-D velocity grid.
 
-    bc[k] = (left, right) with 0 = periodic, 1 = specular wall.
+    bc[k] = (left, right) with 0 = periodic, 1 = specular wall, 2 = diffuse
+    (Maxwell) wall at temperature wall_theta[k][side] moving with
+    wall_vel[k][side].
+    equilibrium: 0 = discretely conservative Maxwellian (Newton), 1 = the
+    continuous Maxwellian sampled at the nodes (non-conservative model).
     mu = mu_ref (theta/theta_ref)^omega, tau = mu / P; mu_ref <= 0 turns the
     collision term off. gamma <= 0 means 5/3.
     """
@@ -84,6 +91,9 @@ class Problem:
     limiter: int = 1
     newton_maxit: int = 20
     newton_tol: float = 1e-14
+    equilibrium: int = 0
+    wall_theta: tuple = ((1.0, 1.0), (1.0, 1.0), (1.0, 1.0))
+    wall_vel: tuple = (((0.0,) * 3,) * 2,) * 3
 
     def cstruct(self) -> _Problem:
         s = _Problem()
@@ -99,6 +109,12 @@ class Problem:
             s.bc[k][0], s.bc[k][1] = int(bck[0]), int(bck[1])
         s.mu_ref, s.theta_ref, s.omega, s.gamma = self.mu_ref, self.theta_ref, self.omega, self.gamma
         s.limiter, s.newton_maxit, s.newton_tol = self.limiter, self.newton_maxit, self.newton_tol
+        s.equilibrium = int(self.equilibrium)
+        for k in range(3):
+            for side in range(2):
+                s.wall_theta[k][side] = float(self.wall_theta[k][side])
+                for c in range(3):
+                    s.wall_vel[k][side][c] = float(self.wall_vel[k][side][c])
         return s
 
     @property

@@ -44,6 +44,9 @@ class Problem(C.Structure):
         ("precision", C.c_int32), ("limiter", C.c_int32),
         ("newton_maxit", C.c_int32),
         ("newton_tol", C.c_double),
+        ("equilibrium", C.c_int32),
+        ("wall_theta", (C.c_double * 2) * 3),
+        ("wall_vel", ((C.c_double * 3) * 2) * 3),
     ]
 
 
@@ -79,6 +82,14 @@ def problem_struct(pb: dict, precision: int = FP64) -> Problem:
     s.omega, s.gamma = float(pb["omega"]), float(pb["gamma"])
     s.precision, s.limiter = int(precision), int(pb["limiter"])
     s.newton_maxit, s.newton_tol = int(pb["newton_maxit"]), float(pb["newton_tol"])
+    s.equilibrium = int(pb.get("equilibrium", 0))
+    wt = pb.get("wall_theta", [(1.0, 1.0)] * 3)
+    wv = pb.get("wall_vel", [((0.0,) * 3,) * 2] * 3)
+    for k in range(3):
+        for side in range(2):
+            s.wall_theta[k][side] = float(wt[k][side])
+            for c in range(3):
+                s.wall_vel[k][side][c] = float(wv[k][side][c])
     return s
 
 

@@ -47,17 +47,20 @@ struct DevGeom {
   double scale[3];  // 2 / h_k
 };
 
-struct DevOps {
-  double D[kMaxN1][kMaxN1];  // D[a][b] = l_b'(xi_a)
-  double lamL[kMaxN1], lamR[kMaxN1];
-  double GL[kMaxN1], GR[kMaxN1];  // correction-function slopes at the nodes
-  double W[kMaxNS];               // tensor-product Gauss weights per node
-  double Wsum;
+template <typename T>
+struct DevOpsT {
+  T D[kMaxN1][kMaxN1];  // D[a][b] = l_b'(xi_a)
+  T lamL[kMaxN1], lamR[kMaxN1];
+  T GL[kMaxN1], GR[kMaxN1];  // correction-function slopes at the nodes
+  T w[kMaxN1];               // 1-D Gauss weights (node weights are products)
+  T Wsum;                    // sum of the node weights
 };
+using DevOps = DevOpsT<double>;
 
 struct StageArgs {
   DevGeom g;
   DevOps op;
+  DevOpsT<float> opf;  // the same operators rounded to FP32 (FP32 arithmetic)
   const void* fin;  // stage input (storage precision)
   const void* fn;   // f^n (storage precision), read when a != 0
   void* out;        // stage output (storage precision), or FP64 residual
@@ -80,6 +83,7 @@ struct NewtonArgs {
   unsigned long long* diag;
   double gamma, mu_ref, theta_ref, omega, tol;
   int32_t maxit, collide, etab_f32;
+  int32_t continuous;  // 1: continuous Maxwellian of (rho, U, theta), no Newton solve
 };
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
@@ -260,11 +264,39 @@ __device__ __forceinline__ double sreg(double x) {
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float sreg(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 __device__ __forceinline__ int sreg(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 template <typename ST> struct Compute;
 template <> struct Compute<double> { using T = double; };
 template <> struct Compute<float> { using T = float; };
+
+// sum_i W_i v_i over the (p+1)^D nodes of a D-dimensional tensor block
+// (D = 1, 2), W_i the product of the 1-D Gauss weights of node i, summed one
+// dimension at a time.
+template <int D, int N1, typename CT>
+__device__ __forceinline__ CT tensor_wsum(const CT* v, const CT* w) {
+  if constexpr (D == 1) {
+    CT s = (CT)0;
+#pragma unroll
+    for (int a = 0; a < N1; ++a) s += sreg(w[a]) * v[a];
+    return s;
+  } else {
+    CT s = (CT)0;
+#pragma unroll
+    for (int b = 0; b < N1; ++b) s += sreg(w[b]) * tensor_wsum<D - 1, N1>(v + b * N1, w);
+    return s;
+  }
+}
+
+// Operators in the arithmetic type (kernel arguments, uniform over the grid).
+template <typename CT>
+__device__ __forceinline__ const DevOpsT<CT>& ops_of(const StageArgs& A) {
+  if constexpr (sizeof(CT) == 8) return A.op;
+  else return A.opf;
+}
 
 // LDS doubles needed by the moment reduction of one element.
 template <int NS>
@@ -351,6 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
   const DevGeom& g = A.g;
+  const DevOpsT<CT>& OP = ops_of<CT>(A);
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
@@ -464,8 +497,8 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     CT lown[N1], lext[N1], Gin[N1];
 #pragma unroll
     for (int bb = 0; bb < N1; ++bb) {
-      const CT lL = (CT)sreg(A.op.lamL[bb]), lR = (CT)sreg(A.op.lamR[bb]);
-      const CT gL = (CT)sreg(A.op.GL[bb]), gR = (CT)sreg(A.op.GR[bb]);
+      const CT lL = sreg(OP.lamL[bb]), lR = sreg(OP.lamR[bb]);
+      const CT gL = sreg(OP.GL[bb]), gR = sreg(OP.GR[bb]);
       lown[bb] = pos[k] ? lL : lR;
       lext[bb] = use_right[k] ? lR : lL;
       Gin[bb] = pos[k] ? gL : gR;
@@ -492,7 +525,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
       for (int ia = 0; ia < N1; ++ia) {
         CT df = (CT)0;
 #pragma unroll
-        for (int bb = 0; bb < N1; ++bb) df += (CT)A.op.D[ia][bb] * line[bb];
+        for (int bb = 0; bb < N1; ++bb) df += OP.D[ia][bb] * line[bb];
         acc[base + ia * S1] += a * df + jump * Gin[ia];
       }
     }
@@ -537,14 +570,10 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
       for (int i = 0; i < NS; ++i) o[i] = cb * (f[i] + dt * L[i]);
     }
     if (A.limiter) {
-      CT mean = (CT)0;
       CT fmin = o[0];
 #pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        mean += (CT)A.op.W[i] * o[i];
-        fmin = o[i] < fmin ? o[i] : fmin;
-      }
-      mean /= (CT)A.op.Wsum;
+      for (int i = 0; i < NS; ++i) fmin = o[i] < fmin ? o[i] : fmin;
+      const CT mean = tensor_wsum<DIM, N1>(o, OP.w) / OP.Wsum;
       const bool hit = valid && (fmin < (CT)0);
       if (hit && mean != fmin) {
         CT beta = fabs(mean / (mean - fmin));

@@ -166,6 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
   const DevGeom& g = A.g;
+  const DevOpsT<CT>& OP = ops_of<CT>(A);
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
@@ -270,8 +271,8 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
     CT lown[N1], lext[N1], Gin[N1];
 #pragma unroll
     for (int bb = 0; bb < N1; ++bb) {
-      const CT lL = (CT)sreg(A.op.lamL[bb]), lR = (CT)sreg(A.op.lamR[bb]);
-      const CT gL = (CT)sreg(A.op.GL[bb]), gR = (CT)sreg(A.op.GR[bb]);
+      const CT lL = sreg(OP.lamL[bb]), lR = sreg(OP.lamR[bb]);
+      const CT gL = sreg(OP.GL[bb]), gR = sreg(OP.GR[bb]);
       lown[bb] = pos[k] ? lL : lR;
       lext[bb] = use_right[k] ? lR : lL;
       Gin[bb] = pos[k] ? gL : gR;
@@ -293,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
       for (int ia = 0; ia < N1; ++ia) {
         CT df = (CT)0;
 #pragma unroll
-        for (int bb = 0; bb < N1; ++bb) df += (CT)sreg(A.op.D[ia][bb]) * line[bb];
+        for (int bb = 0; bb < N1; ++bb) df += sreg(OP.D[ia][bb]) * line[bb];
         acc[base + ia * S1] += a * df + jump * Gin[ia];
       }
     }
@@ -305,15 +306,15 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
     CT lext_mine = (CT)0, gin_mine = (CT)0;
 #pragma unroll
     for (int bb = 0; bb < N1; ++bb) {
-      const CT lL = (CT)sreg(A.op.lamL[bb]), lR = (CT)sreg(A.op.lamR[bb]);
+      const CT lL = sreg(OP.lamL[bb]), lR = sreg(OP.lamR[bb]);
       lown[bb] = pos[2] ? lL : lR;
       const CT le = use_right[2] ? lR : lL;
-      const CT gl = pos[2] ? (CT)sreg(A.op.GL[bb]) : (CT)sreg(A.op.GR[bb]);
+      const CT gl = pos[2] ? sreg(OP.GL[bb]) : sreg(OP.GR[bb]);
       lext_mine = bb == lp ? le : lext_mine;
       gin_mine = bb == lp ? gl : gin_mine;
       CT dr = (CT)0;
 #pragma unroll
-      for (int ia = 0; ia < N1; ++ia) dr = ia == lp ? (CT)sreg(A.op.D[ia][bb]) : dr;
+      for (int ia = 0; ia < N1; ++ia) dr = ia == lp ? sreg(OP.D[ia][bb]) : dr;
       Drow[bb] = dr;
     }
     if (!live) lext_mine = (CT)0;
@@ -371,21 +372,18 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
     }
     if (A.limiter) {
       // element mean and minimum over all planes of the velocity
-      CT part = (CT)0;
+      CT wz = (CT)0;  // Gauss weight of this lane's plane
+#pragma unroll
+      for (int bb = 0; bb < N1; ++bb) wz = bb == lp ? sreg(OP.w[bb]) : wz;
+      CT part = wz * tensor_wsum<2, N1>(o, OP.w);
       CT fmin = o[0];
 #pragma unroll
-      for (int q = 0; q < P2; ++q) {
-        CT wq = (CT)0;  // Gauss weight of node q of this lane's plane
-#pragma unroll
-        for (int bb = 0; bb < N1; ++bb) wq = bb == lp ? (CT)sreg(A.op.W[bb * P2 + q]) : wq;
-        part += wq * o[q];
-        fmin = o[q] < fmin ? o[q] : fmin;
-      }
+      for (int q = 0; q < P2; ++q) fmin = o[q] < fmin ? o[q] : fmin;
       if (!live) {
         part = (CT)0;
         fmin = (CT)INFINITY;
       }
-      const CT mean = group_allsum<G>(part) / (CT)A.op.Wsum;
+      const CT mean = group_allsum<G>(part) / OP.Wsum;
       fmin = group_allmin<G>(fmin);
       const bool hit = valid && (fmin < (CT)0);
       if (hit && mean != fmin) {

@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
     al[4] = -1.0 / th;
     const double sq = rho * sqrt(th);
     const double sc[5] = {rho, sq, sq, sq, Q[4]};
-    for (int it = 0;; ++it) {
+    // the non-conservative model keeps the continuous Maxwellian (no solve)
+    for (int it = 0; !A.continuous; ++it) {
       double S[3][5];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {

@@ -141,19 +141,15 @@ void build_ops(int n1, int dim, DevOps& op) {
     op.GL[a] = -op.lamL[a] / wq[a];
     op.GR[a] = op.lamR[a] / wq[a];
   }
-  int ns = 1;
-  for (int k = 0; k < dim; ++k) ns *= n1;
-  double ws = 0.0;
-  for (int i = 0; i < ns; ++i) {
-    double Wi = 1.0;
-    int r = i;
-    for (int k = 0; k < dim; ++k) {
-      Wi *= wq[r % n1];
-      r /= n1;
-    }
-    op.W[i] = Wi;
+  // node weights are the tensor products w[a_1] ... w[a_d]; their sum is
+  // (sum_a w_a)^d
+  double w1 = 0.0;
+  for (int a = 0; a < n1; ++a) {
+    op.w[a] = wq[a];
+    w1 += wq[a];
   }
-  for (int i = 0; i < ns; ++i) ws += op.W[i];
+  double ws = 1.0;
+  for (int k = 0; k < dim; ++k) ws *= w1;
   op.Wsum = ws;
 }
 
@@ -178,6 +174,8 @@ bgk_status validate(const bgk_problem* pb) {
     return fail(BGK_ERR_INVALID_ARG, "precision must be BGK_FP64 or BGK_FP32");
   if (pb->limiter != 0 && pb->limiter != 1)
     return fail(BGK_ERR_INVALID_ARG, "limiter must be 0 or 1");
+  if (pb->equilibrium != BGK_EQ_CONSERVATIVE && pb->equilibrium != BGK_EQ_CONTINUOUS)
+    return fail(BGK_ERR_INVALID_ARG, "equilibrium must be BGK_EQ_CONSERVATIVE or BGK_EQ_CONTINUOUS");
   for (int k = 0; k < pb->dim; ++k) {
     if (pb->nelem[k] < 1) return fail(BGK_ERR_INVALID_ARG, "nelem[%d] < 1", k);
     if (!(pb->xhi[k] > pb->xlo[k])) return fail(BGK_ERR_INVALID_ARG, "xhi[%d] <= xlo[%d]", k, k);
@@ -286,6 +284,19 @@ StageArgs stage_args(const bgk_solver* s) {
   memset(&A, 0, sizeof(A));
   A.g = s->g;
   A.op = s->op;
+  {
+    const DevOps& o = s->op;
+    DevOpsT<float>& q = A.opf;
+    for (int a = 0; a < kMaxN1; ++a) {
+      for (int b = 0; b < kMaxN1; ++b) q.D[a][b] = (float)o.D[a][b];
+      q.lamL[a] = (float)o.lamL[a];
+      q.lamR[a] = (float)o.lamR[a];
+      q.GL[a] = (float)o.GL[a];
+      q.GR[a] = (float)o.GR[a];
+    }
+    for (int a = 0; a < kMaxN1; ++a) q.w[a] = (float)o.w[a];
+    q.Wsum = (float)o.Wsum;
+  }
   A.params = s->params();
   A.etab = s->etab();
   A.order = s->order_host.empty() ? nullptr : s->order();
@@ -316,6 +327,7 @@ NewtonArgs newton_args(const bgk_solver* s) {
   N.maxit = s->pb.newton_maxit > 0 ? s->pb.newton_maxit : 20;
   N.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
   N.etab_f32 = s->precision == BGK_FP32 ? 1 : 0;
+  N.continuous = s->pb.equilibrium == BGK_EQ_CONTINUOUS ? 1 : 0;
   return N;
 }
 
@@ -872,15 +884,30 @@ struct bgk_batch {
   std::vector<hipEvent_t> joins;
   hipEvent_t fork = nullptr;
   hipGraphExec_t exec = nullptr;
+  // replaced graphs whose last replay may still be executing; destroyed at
+  // the next point where the batch stream has been synchronized
+  std::vector<hipGraphExec_t> retired;
   bool dirty = true;
 };
 
 namespace {
 
+// Destroy the replaced graphs; the batch stream must have been synchronized.
+void release_retired(bgk_batch* b) {
+  for (hipGraphExec_t g : b->retired) (void)hipGraphExecDestroy(g);
+  b->retired.clear();
+}
+
 bgk_status batch_capture(bgk_batch* b) {
   if (b->exec) {
-    HIP_TRY(hipGraphExecDestroy(b->exec));
+    // its last replay may still be running: destroying it now would free
+    // what the device and the runtime still use
+    b->retired.push_back(b->exec);
     b->exec = nullptr;
+    if (b->retired.size() > 16) {  // bound what is held between polls
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      release_retired(b);
+    }
   }
   const size_t n = b->members.size();
   while (b->branches.size() < n) {
@@ -1011,6 +1038,7 @@ bgk_status bgk_batch_poll(bgk_batch* b, bgk_solver** done, int32_t* status, int3
   *ndone = 0;
   if (b->finished.empty()) return BGK_OK;
   HIP_TRY(hipStreamSynchronize(b->stream));
+  release_retired(b);
   int32_t n = 0;
   size_t i = 0;
   for (; i < b->finished.size() && n < cap; ++i) {
@@ -1030,6 +1058,7 @@ bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s) {
   for (size_t i = 0; i < b->members.size(); ++i) {
     if (b->members[i].s == s) {
       HIP_TRY(hipStreamSynchronize(b->stream));
+      release_retired(b);
       s->in_batch = false;
       b->members.erase(b->members.begin() + i);
       b->dirty = true;
@@ -1044,6 +1073,7 @@ int32_t bgk_batch_size(const bgk_batch* b) { return b ? (int32_t)b->members.size
 bgk_status bgk_batch_destroy(bgk_batch* b) {
   if (!b) return BGK_OK;
   (void)hipStreamSynchronize(b->stream);
+  release_retired(b);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   for (auto& m : b->members) m.s->in_batch = false;
   for (auto* s : b->finished) s->in_batch = false;

@@ -5,10 +5,13 @@ from oracle import oracle as orc
 
 KEYS = ["dim", "order", "nelem", "xlo", "xhi", "nvel", "vlo", "vhi", "bc", "mu_ref",
         "theta_ref", "omega", "gamma", "limiter", "newton_maxit", "newton_tol"]
+OPTIONAL = ["equilibrium", "wall_theta", "wall_vel"]
 
 
 def oracle_problem(pb) -> orc.Problem:
-    return orc.Problem(**{k: pb[k] for k in KEYS})
+    kw = {k: pb[k] for k in KEYS}
+    kw.update({k: pb[k] for k in OPTIONAL if k in pb})
+    return orc.Problem(**kw)
 
 
 def initial_state(pb, kind, seed=None, amp=0.0, **prim_kw):

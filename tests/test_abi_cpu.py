@@ -35,6 +35,7 @@ def test_status_strings():
     (lambda p: p.update(bc=[(1, 0), (0, 0), (0, 0)]), 1),
     (lambda p: p.update(vlo=[-5.0, -6.0, -6.0]), 1),   # specular needs symmetric grid
     (lambda p: p.update(limiter=3), 1),
+    (lambda p: p.update(equilibrium=2), 1),
 ])
 def test_footprint_validation(mutate, status):
     pb = wl.sod1d()
@@ -93,3 +94,24 @@ def test_host_geometry_matches_oracle(pb):
     assert np.abs(x - orc.node_coords(pr)).max() < 1e-14
     uo, wo = orc.velocity_grid(pr)
     assert np.array_equal(u, uo) and np.array_equal(w, wo)
+
+
+@pytest.mark.parametrize("pb", [wl.sod1d(nelem=5, order=2), wl.box2d(n=3, order=3),
+                                wl.tgv3d(n=2, order=1)])
+def test_ablation_node_weights_integrate_exactly(pb):
+    """The study's quadrature weights, in the library's node order, integrate
+    low-degree polynomials over the box exactly (checked at the oracle's nodes)."""
+    from oracle import oracle as orc
+    from paper_2308_06196_amd import ablation
+    from tests.helpers import oracle_problem
+    x = orc.node_coords(oracle_problem(pb))
+    W = ablation.node_weights(pb)
+    d = pb["dim"]
+    vol = 1.0
+    for k in range(d):
+        vol *= pb["xhi"][k] - pb["xlo"][k]
+    assert abs(W.sum() - vol) < 1e-12 * vol
+    for k in range(d):
+        lo, hi = pb["xlo"][k], pb["xhi"][k]
+        exact = vol / (hi - lo) * (hi ** 3 - lo ** 3) / 3.0
+        assert abs(W @ x[:, k] ** 2 - exact) < 1e-12 * abs(exact)

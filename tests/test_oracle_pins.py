@@ -176,6 +176,48 @@ def test_collision_moments_vanish_random_field():
     assert rel.max() < 1e-13
 
 
+def _equilibrium_of(pr, f):
+    """g = f + tau C at one node (collision term of the oracle, either model)."""
+    Cc, d = orc.collision(pr, f)
+    Q = orc.moments(pr, f)[0]
+    Pp = (2.0 / 3.0) * (Q[4] - 0.5 * Q[1:4] @ Q[1:4] / Q[0])
+    return f[0, 0] + (pr.mu_ref / Pp) * Cc[0, 0], d
+
+
+def test_continuous_equilibrium_agrees_on_resolved_grid():
+    """Non-conservative model (Sec. 2.1 contrasts it with the DVM equilibrium): on a
+    velocity grid wide and fine enough that the trapezoid moments of Maxwellians are
+    exact to rounding, the continuous Maxwellian of (rho, U, theta) and the discretely
+    conservative one coincide; no Newton iteration is taken."""
+    kw = dict(nelem=(1,), order=0, nvel=(40,) * 3, vlo=(-9.0,) * 3, vhi=(9.0,) * 3)
+    f = orc.maxwellian(P(**kw), np.array([[1.1, 0.15, -0.1, 0.05, 1.0]]))
+    f = f * wl.perturbation(5, f.shape, 0.3)
+    g_cons, _ = _equilibrium_of(P(**kw), f)
+    g_cont, d = _equilibrium_of(P(equilibrium=1, **kw), f)
+    assert np.abs(g_cont - g_cons).max() / np.abs(g_cons).max() < 1e-11
+    assert d["newton_it_max"] == 0 and d["newton_fail"] == 0
+
+
+def test_continuous_equilibrium_does_not_conserve_on_coarse_grid():
+    """On a coarse grid (8^3 over +-4 thermal speeds) the continuous Maxwellian's
+    discrete moments differ from those of f by the quadrature error, so the
+    non-conservative collision term changes mass and energy; the conservative one
+    does not (to rounding)."""
+    kw = dict(nelem=(1,), order=0, nvel=(8,) * 3, vlo=(-4.0,) * 3, vhi=(4.0,) * 3)
+    f = orc.maxwellian(P(**kw), np.array([[1.0, 0.4, 0.0, 0.0, 0.9]]))
+    f = f * wl.perturbation(9, f.shape, 0.3)
+    u, w = orc.velocity_grid(P(**kw))
+    psi = np.column_stack([np.ones(len(u)), u, 0.5 * (u * u).sum(1)])
+    Q = orc.moments(P(**kw), f)[0]
+    scale = np.array([Q[0]] * 4 + [Q[4]])
+    defect = {}
+    for eq in (0, 1):
+        g, _ = _equilibrium_of(P(equilibrium=eq, **kw), f)
+        defect[eq] = np.abs((w[:, None] * psi * (g - f[0, 0])[:, None]).sum(0)) / scale
+    assert defect[0].max() < 1e-13
+    assert defect[1][0] > 1e-4 and defect[1][4] > 1e-4
+
+
 # --------------------------------------------------------------------------
 # Homogeneous relaxation: SSP-RK3 on C alone has a closed form
 # --------------------------------------------------------------------------
