@@ -33,6 +33,11 @@
  *     scaled moment residual is <= tol, then takes one final polishing step;
  *     a step that would make alpha_4 >= 0 is halved until alpha_4 < 0;
  *   - specular walls mirror the wall-normal velocity component;
+ *   - diffuse (Maxwell, fully accommodating) walls re-emit, into the
+ *     velocities pointing away from the wall, the wall Maxwellian sampled at
+ *     the nodes, scaled at every flux point so that the discrete mass flux
+ *     through the wall vanishes (the paper defers wall conditions to another
+ *     work);
  *   - the limiter acts after every Runge-Kutta stage on the solution nodes,
  *     with the Gauss-weighted element mean.
  *
@@ -515,6 +520,41 @@ static int64_t neighbour(const orc_problem* pr, const orc_ops* op, int64_t e, in
 }
 
 /* T[i*nv + j] = discrete (u_j . grad f) at node i of element e. */
+/* Unit-density Maxwellian of the diffuse wall on side `side` of axis k at
+ * velocity u (wall temperature and velocity from the problem). */
+static double wall_maxwellian(const orc_problem* pr, int k, int side, const double* u) {
+  double th = pr->wall_theta[k][side];
+  const double* U = pr->wall_vel[k][side];
+  double d2 = 0.0;
+  for (int c = 0; c < 3; ++c) d2 += (u[c] - U[c]) * (u[c] - U[c]);
+  return exp(-d2 / (2.0 * th)) / pow(2.0 * M_PI * th, 1.5);
+}
+
+/* Density of the gas re-emitted by a diffuse wall at one flux point (reading
+ * in the header): the discrete mass flux leaving the domain through the wall,
+ * sum over outgoing velocities of w |u_k| f_trace, divided by the flux the
+ * unit-density wall Maxwellian carries back in, so the net mass flux through
+ * the wall is zero. side 0 = left face (outgoing: u_k < 0), 1 = right face. */
+static double wall_density(const orc_problem* pr, const orc_ops* op, const double* fe, int k,
+                           int side, int base, int stride) {
+  const int n1 = op->n1;
+  const int64_t nv = op->nv;
+  const double* lam = side == 0 ? op->lamL : op->lamR;
+  double out = 0.0, in = 0.0;
+  for (int64_t j = 0; j < nv; ++j) {
+    double a = op->u[3 * j + k];
+    int outgoing = side == 0 ? a < 0.0 : a > 0.0;
+    if (outgoing) {
+      double tr = 0.0;
+      for (int b = 0; b < n1; ++b) tr += lam[b] * fe[(base + b * stride) * nv + j];
+      out += op->w[j] * fabs(a) * tr;
+    } else if (a != 0.0) {
+      in += op->w[j] * fabs(a) * wall_maxwellian(pr, k, side, op->u + 3 * j);
+    }
+  }
+  return out / in;
+}
+
 static void element_transport(const orc_problem* pr, const orc_ops* op, const double* f, int64_t e,
                               double* T) {
   const int n1 = op->n1, ns = op->ns;
@@ -529,8 +569,11 @@ static void element_transport(const orc_problem* pr, const orc_ops* op, const do
     const double* fL_el = eL >= 0 ? f + eL * ns * nv : NULL;
     const double* fR_el = eR >= 0 ? f + eR * ns * nv : NULL;
     double sk = 2.0 / op->h[k];
+    const int diffL = !fL_el && pr->bc[k][0] == 2, diffR = !fR_el && pr->bc[k][1] == 2;
     for (int base = 0; base < ns; ++base) {
       if ((base / stride) % n1 != 0) continue; /* first node of a line along k */
+      double rhoL = diffL ? wall_density(pr, op, fe, k, 0, base, stride) : 0.0;
+      double rhoR = diffR ? wall_density(pr, op, fe, k, 1, base, stride) : 0.0;
       for (int64_t j = 0; j < nv; ++j) {
         double a = op->u[3 * j + k];
         double line[ORC_MAXN];
@@ -541,16 +584,21 @@ static void element_transport(const orc_problem* pr, const orc_ops* op, const do
           fRo += op->lamR[b] * line[b];
         }
         /* exterior trace at the left face: right trace of the left neighbour,
-         * or at a specular wall the own left trace at the mirrored velocity */
+         * at a specular wall the own left trace at the mirrored velocity, at a
+         * diffuse wall the re-emitted wall Maxwellian */
         double extL = 0.0, extR = 0.0;
         if (fL_el) {
           for (int b = 0; b < n1; ++b) extL += op->lamR[b] * fL_el[(base + b * stride) * nv + j];
+        } else if (diffL) {
+          extL = rhoL * wall_maxwellian(pr, k, 0, op->u + 3 * j);
         } else {
           int64_t jm = mirror_vel(op, j, k);
           for (int b = 0; b < n1; ++b) extL += op->lamL[b] * fe[(base + b * stride) * nv + jm];
         }
         if (fR_el) {
           for (int b = 0; b < n1; ++b) extR += op->lamL[b] * fR_el[(base + b * stride) * nv + j];
+        } else if (diffR) {
+          extR = rhoR * wall_maxwellian(pr, k, 1, op->u + 3 * j);
         } else {
           int64_t jm = mirror_vel(op, j, k);
           for (int b = 0; b < n1; ++b) extR += op->lamR[b] * fe[(base + b * stride) * nv + jm];

@@ -22,6 +22,9 @@ meshes and reference data that are not available, these stand in for them):
           16^3 on [-5,5]^3, Mach 0.1, isothermal, Kn=1e-3.
   mach2   3-D periodic box [0,1]^3, 32^3 elements, p=2, 20^3 on [-8,8]^3,
           Mach-2 stream plus 5 % random-phase density/temperature modes.
+  channel2d  Couette channel [0,1]^2, periodic in x, diffuse walls at y = 0, 1
+          moving with -/+ 0.2 along x at unit temperature; gas initially at
+          rest (8x8 elements, p=2, 12^3 on [-6,6]^3, Kn=1e-2 by default).
 """
 from __future__ import annotations
 
@@ -74,6 +77,16 @@ def tgv3d(n=16, order=3, nv1=16, vmax=5.0, kn=1e-3):
 
 def mach2(n=32, order=2, nv1=20, vmax=8.0, kn=1e-2):
     return problem(3, order, [n] * 3, [0.0] * 3, [1.0] * 3, [nv1] * 3, [-vmax] * 3, [vmax] * 3, kn)
+
+
+def channel2d(nx=8, ny=8, order=2, nv1=12, vmax=6.0, kn=1e-2, uw=0.2, theta_w=1.0):
+    """Couette channel: periodic in x, diffuse (Maxwell) walls at y = 0 and
+    y = 1 moving with -uw and +uw along x at temperature theta_w."""
+    pb = problem(2, order, [nx, ny], [0.0, 0.0], [1.0, 1.0], [nv1] * 3, [-vmax] * 3,
+                 [vmax] * 3, kn, bc=[(0, 0), (2, 2)])
+    pb["wall_theta"] = [(1.0, 1.0), (theta_w, theta_w), (1.0, 1.0)]
+    pb["wall_vel"] = [((0.0,) * 3,) * 2, ((-uw, 0.0, 0.0), (uw, 0.0, 0.0)), ((0.0,) * 3,) * 2]
+    return pb
 
 
 # --------------------------------------------------------------------------
@@ -135,7 +148,17 @@ def prim_mach2(x, seed=0):
     return prim
 
 
-PRIM = {"sod1d": prim_sod, "box2d": prim_box2d, "tgv3d": prim_tgv3d, "mach2": prim_mach2}
+def prim_channel(x, amp=0.0, k=1, phase=0.0):
+    """Gas at rest at unit temperature; optional seeded density modulation along
+    the channel, rho = 1 + amp sin(2 pi k x + phase)."""
+    prim = np.zeros((len(x), 5))
+    prim[:, 0] = 1.0 + amp * np.sin(2 * math.pi * k * x[:, 0] + phase)
+    prim[:, 4] = 1.0
+    return prim
+
+
+PRIM = {"sod1d": prim_sod, "box2d": prim_box2d, "tgv3d": prim_tgv3d, "mach2": prim_mach2,
+        "channel2d": prim_channel}
 
 
 def perturbation(seed: int, shape, amp: float = 0.3) -> np.ndarray:

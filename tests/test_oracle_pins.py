@@ -396,3 +396,59 @@ def test_specular_walls_conserve_mass_and_energy():
     assert abs(t1[4] - t0[4]) / t0[4] < 1e-13
     # transverse momentum stays zero by symmetry of the velocity grid
     assert np.abs(t1[2:4]).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Diffuse (Maxwell) walls: the re-emitted gas carries back exactly the mass
+# that reaches the wall
+# --------------------------------------------------------------------------
+
+def _channel(**kw):
+    from tests.helpers import oracle_problem
+    pb = wl.channel2d(nx=3, ny=3, order=2, nv1=8, **kw)
+    return pb, oracle_problem(pb)
+
+
+def test_diffuse_walls_conserve_mass_and_exchange_energy():
+    """Hot moving walls: total mass is conserved to rounding (zero net mass flux at
+    every wall flux point), while energy flows in from the walls."""
+    pb, pr = _channel(theta_w=1.5, uw=0.3)
+    f = orc.maxwellian(pr, wl.prim_channel(orc.node_coords(pr), amp=0.2, k=1))
+    f *= wl.perturbation(4, f.shape, 0.1)
+    t0 = _totals(pr, f)
+    dt = orc.stable_dt(pr, f, 0.1)
+    f1, d = orc.rk3_step(pr, f, dt, 5)
+    t1 = _totals(pr, f1)
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-13
+    assert t1[4] > t0[4] * (1 + 1e-4)
+    assert d["newton_fail"] == 0
+
+
+def test_diffuse_wall_equilibrium_is_steady():
+    """Gas at rest in the wall Maxwellian (walls at rest, same temperature) on a
+    symmetric velocity grid: the wall re-emits exactly the interior state, so the
+    transport operator vanishes to rounding."""
+    pb, pr = _channel(theta_w=1.2, uw=0.0)
+    prim = np.tile([1.3, 0.0, 0.0, 0.0, 1.2], (pr.nx, 1))
+    f = orc.maxwellian(pr, prim)
+    T = orc.transport(pr, f)
+    scale = np.abs(f).max() * 6.0 * 2.0 / (1.0 / 3.0)  # max|u| * 2/h * max|f|
+    assert np.abs(T).max() / scale < 1e-14
+
+
+def test_diffuse_walls_drag_the_gas():
+    """Walls moving with -U (bottom) and +U (top) along x: after a few steps the gas
+    near the top wall moves with +x momentum, near the bottom with -x, and the total
+    x momentum stays zero by symmetry; cold walls cool the gas."""
+    pb, pr = _channel(theta_w=0.8, uw=0.3)
+    f = orc.maxwellian(pr, wl.prim_channel(orc.node_coords(pr)))
+    t0 = _totals(pr, f)
+    dt = orc.stable_dt(pr, f, 0.1)
+    f1, _ = orc.rk3_step(pr, f, dt, 5)
+    x = orc.node_coords(pr)
+    Q = orc.moments(pr, f1)
+    assert Q[x[:, 1] > 0.8, 1].mean() > 1e-4
+    assert Q[x[:, 1] < 0.2, 1].mean() < -1e-4
+    t1 = _totals(pr, f1)
+    assert abs(t1[1]) < 1e-13 * t1[0]
+    assert t1[4] < t0[4] * (1 - 1e-4)
