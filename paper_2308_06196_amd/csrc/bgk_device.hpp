@@ -72,6 +72,30 @@ struct StageArgs {
   double dt, a, b;
   int64_t e0, ecount, out_e0;
   int32_t limiter, collide;
+  // diffuse walls (1-D/2-D): wallp[k][s][8] = ((2 pi theta_w)^{-3/2},
+  // 1/(2 theta_w), U_w, 1/(incoming flux of the unit wall Maxwellian)), the
+  // re-emitted density of every wall flux point, and the offset of side
+  // (k, s) in it (-1: not a diffuse wall)
+  const double* wallp;
+  const double* wall_rho;
+  int32_t wall_off[2][2];
+};
+
+// Diffuse walls: outgoing mass flux per wall flux point and velocity chunk
+// (k_wall_flux), then the re-emitted density per flux point (k_wall_rho).
+// Sides are listed in order; side q covers nface[q] elements of the wall,
+// each with (p+1)^(d-1) flux points starting at off[q] in wall_rho.
+struct WallArgs {
+  DevGeom g;
+  double lamL[kMaxN1], lamR[kMaxN1];
+  const void* fin;       // stage input (storage precision)
+  const double* wallp;   // [k][s][8], see StageArgs
+  double* part;          // [flux point][chunk] partial sums
+  double* rho;           // [flux point] re-emitted density
+  int32_t nside;
+  int32_t side_k[4], side_s[4], off[4], nface[4];
+  int32_t blk0[5];       // first block of every side (k_wall_flux)
+  int32_t npoints;       // flux points over all sides
 };
 
 struct NewtonArgs {
@@ -412,9 +436,11 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   // otherwise) or, at a specular wall, the own element at the velocity with
   // component k mirrored; the exterior trace is the neighbour's right trace
   // (u_k > 0), its left trace (u_k < 0), or the own trace on the wall side.
+  // At a diffuse wall the exterior state is the re-emitted wall Maxwellian
+  // (dif[k]; the loads then read the own element and go unused).
   const ST* __restrict__ fin = (const ST*)A.fin;
   const ST* src[DIM];
-  bool pos[DIM], use_right[DIM];
+  bool pos[DIM], use_right[DIM], dif[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     pos[k] = vel.u[k] * g.scale[k] > 0.0;
@@ -426,9 +452,12 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
       wall = pos[k] ? wall_lo : wall_hi;
       nk = (nk + nek) % nek;
     }
+    dif[k] = wall && (pos[k] ? sreg(g.bc[k][0]) : sreg(g.bc[k][1])) == 2;
     int64_t src_e = e;
     int src_j = jj;
-    if (wall) {
+    if (dif[k]) {
+      // own element, own velocity (unused values)
+    } else if (wall) {
       int bm[3] = {vel.b[0], vel.b[1], vel.b[2]};
       bm[k] = g.nv1[k] - 1 - bm[k];
       src_j = bm[0] + g.nv1[0] * (bm[1] + g.nv1[1] * bm[2]);
@@ -503,6 +532,27 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
       lext[bb] = use_right[k] ? lR : lL;
       Gin[bb] = pos[k] ? gL : gR;
     }
+    // diffuse walls of this axis touching the element (uniform)
+    const double* rho_lo = nullptr;
+    const double* rho_hi = nullptr;
+    bool dwall = false;
+    CT mw = (CT)0;
+    if constexpr (DIM <= 2) {
+      const int off_lo = sreg(A.wall_off[k][0]), off_hi = sreg(A.wall_off[k][1]);
+      const bool dlo = off_lo >= 0 && ek[k] == 0;
+      const bool dhi = off_hi >= 0 && ek[k] == sreg(g.nelem[k]) - 1;
+      dwall = dlo || dhi;
+      if (dwall) {
+        constexpr int NF = ipow(N1, DIM - 1);
+        const int fe = DIM == 1 ? 0 : ek[1 - k];  // element index on the wall face
+        rho_lo = A.wall_rho + (dlo ? off_lo : 0) + fe * NF;
+        rho_hi = A.wall_rho + (dhi ? off_hi : 0) + fe * NF;
+        // unit-density wall Maxwellian at this lane's velocity, inflow side
+        const double* wp = A.wallp + (k * 2 + (pos[k] ? 0 : 1)) * 8;
+        const double d0 = vel.u[0] - wp[2], d1 = vel.u[1] - wp[3], d2 = vel.u[2] - wp[4];
+        mw = (CT)(wp[0] * exp(-(d0 * d0 + d1 * d1 + d2 * d2) * wp[1]));
+      }
+    }
 #pragma unroll
     for (int base = 0; base < NS; ++base) {
       if ((base / S1) % N1 != 0) continue;
@@ -519,6 +569,12 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
         else
           xv = (CT)src[k][(int64_t)(base + bb * S1) * nv];
         ext += lext[bb] * xv;
+      }
+      if (dwall) {  // uniform: the element touches a diffuse wall of axis k
+        // flux point of this line on the wall face
+        const int fp = (base % S1) + (base / (S1 * N1)) * S1;
+        const CT rw = (CT)(pos[k] ? sreg(rho_lo[fp]) : sreg(rho_hi[fp]));
+        ext = dif[k] ? rw * mw : ext;
       }
       const CT jump = a * (ext - own);
 #pragma unroll

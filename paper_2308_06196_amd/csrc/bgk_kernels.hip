@@ -291,6 +291,87 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const 
   for (int m = 0; m < 5; ++m) Q[node * 5 + m] = q[m];
 }
 
+// ---------------------------------------------------------------------------
+// Diffuse walls. At a flux point of a wall face the gas leaving the domain
+// carries the discrete mass flux sum_{outgoing j} w_j |u_k| f_trace; the wall
+// re-emits rho_w times the unit wall Maxwellian into the incoming velocities,
+// with rho_w = that flux / (incoming flux of the unit wall Maxwellian), so the
+// net mass flux through the wall vanishes.
+// ---------------------------------------------------------------------------
+
+// One work-group = one wall-face element x one chunk of 256 velocities; the
+// flux points' partial sums are reduced in a fixed order (lanes by an xor
+// butterfly, then the four waves in LDS).
+template <int DIM, int P, typename ST>
+__global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
+  constexpr int N1 = P + 1;
+  constexpr int NS = ipow(N1, DIM);
+  constexpr int NF = ipow(N1, DIM - 1);
+  __shared__ double red[kBlock / 64][NF];
+  const DevGeom& g = W.g;
+  const int b = blockIdx.x;
+  int q = 0;
+  while (q + 1 < W.nside && b >= W.blk0[q + 1]) ++q;
+  const int k = W.side_k[q], side = W.side_s[q];
+  const int local = b - W.blk0[q];
+  const int face = local / g.nchunk, chunk = local % g.nchunk;
+  // element: coordinate k on the wall, the other coordinate (2-D) = face
+  int ek[2] = {0, 0};
+  ek[k] = side == 0 ? 0 : g.nelem[k] - 1;
+  if (DIM == 2) ek[1 - k] = face;
+  const int64_t e = ek[0] + (int64_t)g.nelem[0] * ek[1];
+  const int64_t nv = g.nv;
+  const int j = chunk * kBlock + (int)threadIdx.x;
+  const bool valid = j < nv;
+  const int jj = valid ? j : (int)nv - 1;
+  const Vel vel = velocity_of(g, jj);
+  const double a = vel.u[k];
+  const bool outgoing = valid && (side == 0 ? a < 0.0 : a > 0.0);
+  const double wt = outgoing ? vel.w * fabs(a) : 0.0;
+  const int S1 = k == 0 ? 1 : N1;
+  const ST* fe = (const ST*)W.fin + e * NS * nv + jj;
+  double v[NF];
+#pragma unroll
+  for (int fp = 0; fp < NF; ++fp) {
+    const int base = (fp % S1) + (fp / S1) * S1 * N1;
+    double tr = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < N1; ++bb)
+      tr += (side == 0 ? W.lamL[bb] : W.lamR[bb]) * (double)fe[(int64_t)(base + bb * S1) * nv];
+    v[fp] = wt * tr;
+  }
+#pragma unroll
+  for (int fp = 0; fp < NF; ++fp) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[fp] += __shfl_xor(v[fp], o, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int fp = 0; fp < NF; ++fp) red[wave][fp] = v[fp];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NF) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) sum += red[w][threadIdx.x];
+    W.part[((int64_t)W.off[q] + face * NF + threadIdx.x) * g.nchunk + chunk] = sum;
+  }
+}
+
+// rho_w per wall flux point: the chunk partials summed in order, times the
+// inverse incoming flux of the side's unit wall Maxwellian.
+__global__ void __launch_bounds__(256) k_wall_rho(const WallArgs W) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W.npoints) return;
+  int q = 0;
+  while (q + 1 < W.nside && t >= W.off[q + 1]) ++q;
+  const double* p = W.part + (int64_t)t * W.g.nchunk;
+  double sum = 0.0;
+  for (int c = 0; c < W.g.nchunk; ++c) sum += p[c];
+  W.rho[t] = sum * W.wallp[(W.side_k[q] * 2 + W.side_s[q]) * 8 + 5];
+}
+
 // Continuous Maxwellian sampled at every (node, velocity); one work-group =
 // one node x one velocity chunk.
 // grid-stride over (node, velocity chunk) work items: the number of work
@@ -371,6 +452,31 @@ int velocities_per_block(int dim, int order) {
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s) {
   if (A.ecount <= 0) return hipSuccess;
   return precision == 0 ? stage_dispatch<double>(mode, A, s) : stage_dispatch<float>(mode, A, s);
+}
+
+template <typename ST>
+static hipError_t wall_dispatch(const WallArgs& W, hipStream_t s) {
+  const dim3 grid((unsigned)W.blk0[W.nside]), block(kBlock);
+  switch (W.g.dim * 10 + (W.g.n1 - 1)) {
+#define BGK_WALL(D, P)                                                          \
+  case D * 10 + P:                                                              \
+    hipLaunchKernelGGL((k_wall_flux<D, P, ST>), grid, block, 0, s, W);          \
+    break;
+    BGK_WALL(1, 1) BGK_WALL(1, 2) BGK_WALL(1, 3)
+    BGK_WALL(2, 1) BGK_WALL(2, 2) BGK_WALL(2, 3)
+#undef BGK_WALL
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wall_rho, dim3(grid_of(W.npoints, 256)), dim3(256), 0, s, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall(int precision, const WallArgs& W, hipStream_t s) {
+  if (W.nside == 0) return hipSuccess;
+  return precision == 0 ? wall_dispatch<double>(W, s) : wall_dispatch<float>(W, s);
 }
 
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {

@@ -19,6 +19,8 @@ int velocities_per_block(int dim, int order);
 // 1: residual L(f) in FP64; 2: moment partials only.
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s);
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s);
+// Re-emitted densities of the diffuse-wall flux points of the stage input.
+hipError_t launch_wall(int precision, const WallArgs& W, hipStream_t s);
 hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,
                                   hipStream_t s);
 hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,

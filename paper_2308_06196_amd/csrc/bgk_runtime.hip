@@ -159,11 +159,24 @@ void gauss_nodes(int n1, double* xi) {
 }
 
 struct Layout {
-  size_t f[3], partials, params, etab, order, Q, prim, diag, total;
+  size_t f[3], partials, params, etab, order, Q, prim, diag, wallp, wall_part, wall_rho, total;
   int64_t nx, nv, ne;
   int ns, nchunk;
+  int64_t wall_points;  // flux points on diffuse walls
   size_t fbytes;
 };
+
+// Flux points of the diffuse walls: side (k, s) holds ne / nelem[k] faces of
+// (p+1)^(d-1) points each.
+int64_t diffuse_wall_points(const bgk_problem* pb) {
+  int64_t ne = 1, nf = 1, n = 0;
+  for (int k = 0; k < pb->dim; ++k) ne *= pb->nelem[k];
+  for (int k = 0; k + 1 < pb->dim; ++k) nf *= pb->order + 1;
+  for (int k = 0; k < pb->dim; ++k)
+    for (int s = 0; s < 2; ++s)
+      if (pb->bc[k][s] == BGK_BC_DIFFUSE) n += ne / pb->nelem[k] * nf;
+  return n;
+}
 
 bgk_status validate(const bgk_problem* pb) {
   if (!pb) return fail(BGK_ERR_INVALID_ARG, "problem is NULL");
@@ -179,9 +192,17 @@ bgk_status validate(const bgk_problem* pb) {
   for (int k = 0; k < pb->dim; ++k) {
     if (pb->nelem[k] < 1) return fail(BGK_ERR_INVALID_ARG, "nelem[%d] < 1", k);
     if (!(pb->xhi[k] > pb->xlo[k])) return fail(BGK_ERR_INVALID_ARG, "xhi[%d] <= xlo[%d]", k, k);
-    for (int s = 0; s < 2; ++s)
-      if (pb->bc[k][s] != BGK_BC_PERIODIC && pb->bc[k][s] != BGK_BC_SPECULAR)
+    for (int s = 0; s < 2; ++s) {
+      if (pb->bc[k][s] != BGK_BC_PERIODIC && pb->bc[k][s] != BGK_BC_SPECULAR &&
+          pb->bc[k][s] != BGK_BC_DIFFUSE)
         return fail(BGK_ERR_INVALID_ARG, "bc[%d][%d] unknown", k, s);
+      if (pb->bc[k][s] == BGK_BC_DIFFUSE) {
+        if (pb->dim == 3)
+          return fail(BGK_ERR_UNSUPPORTED, "diffuse walls are built for 1-D and 2-D meshes");
+        if (!(pb->wall_theta[k][s] > 0.0))
+          return fail(BGK_ERR_INVALID_ARG, "wall_theta[%d][%d] must be > 0", k, s);
+      }
+    }
     if ((pb->bc[k][0] == BGK_BC_PERIODIC) != (pb->bc[k][1] == BGK_BC_PERIODIC))
       return fail(BGK_ERR_INVALID_ARG, "axis %d: periodic on one side only", k);
     if (pb->bc[k][0] == BGK_BC_SPECULAR && pb->vlo[k] != -pb->vhi[k])
@@ -238,6 +259,13 @@ Layout layout_of(const bgk_problem* pb) {
   off = align_up(off + (size_t)L.nx * 5 * sizeof(double));
   L.diag = off;
   off = align_up(off + 8 * sizeof(unsigned long long));
+  L.wall_points = diffuse_wall_points(pb);
+  L.wallp = off;
+  off = align_up(off + (L.wall_points ? 32 * sizeof(double) : 0));
+  L.wall_part = off;
+  off = align_up(off + (size_t)L.wall_points * L.nchunk * sizeof(double));
+  L.wall_rho = off;
+  off = align_up(off + (size_t)L.wall_points * sizeof(double));
   L.total = off;
   return L;
 }
@@ -271,6 +299,11 @@ struct bgk_solver {
   int32_t* order() const { return (int32_t*)(ws + L.order); }
   bool order_ready = false;
   std::vector<int32_t> order_host;  // traversal order (empty: lexicographic)
+  std::vector<double> wallp_host;   // [k][s][8] diffuse-wall constants (empty: none)
+  WallArgs wall;                    // sides of the diffuse walls (fin set per stage)
+  double* wallp() const { return (double*)(ws + L.wallp); }
+  double* wall_part() const { return (double*)(ws + L.wall_part); }
+  double* wall_rho() const { return (double*)(ws + L.wall_rho); }
   double* Q() const { return (double*)(ws + L.Q); }
   double* prim() const { return (double*)(ws + L.prim); }
   unsigned long long* diag() const { return (unsigned long long*)(ws + L.diag); }
@@ -307,6 +340,14 @@ StageArgs stage_args(const bgk_solver* s) {
   A.out_e0 = 0;
   A.limiter = s->pb.limiter;
   A.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
+  for (int k = 0; k < 2; ++k)
+    for (int sd = 0; sd < 2; ++sd) A.wall_off[k][sd] = -1;
+  if (s->wall.nside) {
+    A.wallp = s->wallp();
+    A.wall_rho = s->wall_rho();
+    for (int q = 0; q < s->wall.nside; ++q)
+      A.wall_off[s->wall.side_k[q]][s->wall.side_s[q]] = s->wall.off[q];
+  }
   return A;
 }
 
@@ -345,9 +386,91 @@ bgk_status ensure_counters(bgk_solver* s) {
                              s->order_host.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                              s->stream));
     }
+    if (!s->wallp_host.empty()) {
+      HIP_TRY(hipMemcpyAsync(s->wallp(), s->wallp_host.data(),
+                             s->wallp_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                             s->stream));
+    }
     s->order_ready = true;
   }
   return BGK_OK;
+}
+
+// Diffuse walls of the stage input fin: re-emitted density per flux point.
+bgk_status wall_densities(bgk_solver* s, const void* fin, hipStream_t st) {
+  if (!s->wall.nside) return BGK_OK;
+  WallArgs W = s->wall;
+  W.fin = fin;
+  HIP_TRY(launch_wall(s->precision, W, st));
+  return BGK_OK;
+}
+
+// Sides, offsets and constants of the diffuse walls (host, at create). For
+// side (k, s): (2 pi theta_w)^{-3/2}, 1/(2 theta_w), U_w and the inverse of
+// the incoming flux sum_{incoming j} w_j |u_k| M_w(u_j) of the unit wall
+// Maxwellian (incoming: u_k > 0 at s = 0, u_k < 0 at s = 1).
+void setup_walls(bgk_solver* s) {
+  const bgk_problem* pb = &s->pb;
+  WallArgs& W = s->wall;
+  memset(&W, 0, sizeof(W));
+  if (!s->L.wall_points) return;
+  W.g = s->g;
+  for (int b = 0; b < kMaxN1; ++b) {
+    W.lamL[b] = s->op.lamL[b];
+    W.lamR[b] = s->op.lamR[b];
+  }
+  W.wallp = s->wallp();
+  W.part = s->wall_part();
+  W.rho = s->wall_rho();
+  s->wallp_host.assign(32, 0.0);
+  int nf = 1;
+  for (int k = 0; k + 1 < pb->dim; ++k) nf *= pb->order + 1;
+  int off = 0, blk = 0;
+  for (int k = 0; k < pb->dim; ++k) {
+    for (int sd = 0; sd < 2; ++sd) {
+      if (pb->bc[k][sd] != BGK_BC_DIFFUSE) continue;
+      const int q = W.nside++;
+      const int nface = (int)(s->L.ne / pb->nelem[k]);
+      W.side_k[q] = k;
+      W.side_s[q] = sd;
+      W.off[q] = off;
+      W.nface[q] = nface;
+      W.blk0[q] = blk;
+      off += nface * nf;
+      blk += nface * s->L.nchunk;
+      const double th = pb->wall_theta[k][sd];
+      const double* U = pb->wall_vel[k][sd];
+      const double norm = 1.0 / pow(2.0 * M_PI * th, 1.5), i2t = 1.0 / (2.0 * th);
+      const DevGeom& g = s->g;
+      double in = 0.0;
+      for (int bz = 0; bz < g.nv1[2]; ++bz)
+        for (int by = 0; by < g.nv1[1]; ++by)
+          for (int bx = 0; bx < g.nv1[0]; ++bx) {
+            const int b[3] = {bx, by, bz};
+            double u[3], w = 1.0;
+            for (int c = 0; c < 3; ++c) {
+              u[c] = g.vlo[c] + b[c] * g.du[c];
+              double wc = g.du[c];
+              if (b[c] == 0 || b[c] == g.nv1[c] - 1) wc *= 0.5;
+              w *= wc;
+            }
+            const double a = u[k];
+            if (sd == 0 ? !(a > 0.0) : !(a < 0.0)) continue;
+            const double d2 = (u[0] - U[0]) * (u[0] - U[0]) + (u[1] - U[1]) * (u[1] - U[1]) +
+                              (u[2] - U[2]) * (u[2] - U[2]);
+            in += w * fabs(a) * norm * exp(-d2 * i2t);
+          }
+      double* c = s->wallp_host.data() + (k * 2 + sd) * 8;
+      c[0] = norm;
+      c[1] = i2t;
+      c[2] = U[0];
+      c[3] = U[1];
+      c[4] = U[2];
+      c[5] = 1.0 / in;
+    }
+  }
+  W.blk0[W.nside] = blk;  // end of the last side's blocks
+  W.npoints = off;
 }
 
 // Brick traversal of a hexahedral mesh: bricks of 4 x 4 x 4 elements
@@ -530,6 +653,7 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
   g.nchunk = s->L.nchunk;
   build_ops(g.n1, g.dim, s->op);
   if (pb->dim == 3) brick_order(g.nelem, s->order_host);
+  setup_walls(s);
   *out = s;
   return BGK_OK;
 }
@@ -671,6 +795,10 @@ bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_
   }
   NewtonArgs N = newton_args(s);
   HIP_TRY(launch_newton(N, s->stream));
+  {
+    bgk_status st = wall_densities(s, fin, s->stream);
+    if (st) return st;
+  }
   StageArgs A = stage_args(s);
   A.fin = fin;
   if (where == BGK_DEVICE) {
@@ -719,6 +847,7 @@ bgk_status rk3_launch(bgk_solver* s, double dt, int32_t nsteps, hipStream_t st, 
   for (int32_t step = 0; step < nsteps; ++step) {
     for (int k = 0; k < 3; ++k) {
       HIP_TRY(launch_newton(N, st));
+      if ((rc = wall_densities(s, s->f(k), st))) return rc;
       if (timed) {
         s->kinds.push_back(0);
         if ((rc = mark(s))) return rc;
