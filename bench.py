@@ -143,7 +143,8 @@ def cpu_baseline(pb_full, prim_fn, budget_s=12.0):
                       f"direct velocity sums"}
 
 
-def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4):
+def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4,
+            kinds=("sod1d", "box2d")):
     """Serving mix (shock tubes and periodic boxes, p in 1..3, 8^3..32^3 velocities,
     Kn log-uniform [1e-4, 1], 100 steps each). A saturating run (all requests at
     t = 0) measures the capacity; then the same requests arrive as a Poisson
@@ -156,7 +157,7 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4)
 
     def reqs(rate):
         return serve.make_requests(wl.serving_requests(n=n_requests, seed=seed, rate=rate,
-                                                       steps=steps))
+                                                       steps=steps, kinds=kinds))
 
     def batched(rate):
         ex = serve.BatchExecutor(max_members=max_members)
@@ -169,7 +170,7 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4)
     pois = batched(0.8 * cap_rate)
     seq_sat = serve.run_sequential(reqs(None))
     seq_pois = serve.run_sequential(reqs(0.8 * cap_rate))
-    return {"requests": n_requests, "steps_each": steps,
+    return {"requests": n_requests, "steps_each": steps, "kinds": list(kinds),
             "total_dof": int(sum(r.dof for r in reqs(None))),
             "capacity_requests_per_s": cap_rate, "poisson_rate_per_s": 0.8 * cap_rate,
             "batched_saturating": sat, "batched_poisson": pois,
@@ -189,6 +190,8 @@ def main():
     ap.add_argument("--serving", type=int, default=24, metavar="N",
                     help="requests in the serving mix (0: skip)")
     ap.add_argument("--serving-steps", type=int, default=100)
+    ap.add_argument("--serving-kinds", default="sod1d,box2d",
+                    help="request kinds of the serving mix (sod1d, box2d, channel2d)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "calibrates the HBM byte counters against a known traffic")
@@ -228,7 +231,7 @@ def main():
         line["mixed"] = {"dtype": "f32-bulk/f64-collision", "value": mx["value"],
                          "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps)}
     if a.serving:
-        sv = serving(a.serving, a.serving_steps)
+        sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")))
         line["serving"] = sv
         p, q = sv["batched_poisson"], sv["sequential_fp64_poisson"]
         print(f"[bench] serving {a.serving} requests: batched p50 {p['p50_s']:.3f} s, p99 "

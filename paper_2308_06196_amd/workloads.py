@@ -171,9 +171,12 @@ def perturbation(seed: int, shape, amp: float = 0.3) -> np.ndarray:
 # Serving mix: Poisson arrivals of shock-tube and periodic-box requests
 # --------------------------------------------------------------------------
 
-def serving_requests(n=256, seed=0, rate=None, nv_choices=(8, 16, 24, 32), steps=100):
-    """Request descriptors drawn uniformly from {1-D shock tube with 32..512
-    elements, 2-D periodic box with 16^2..64^2 elements}; p in {1,2,3}; N_1d from
+def serving_requests(n=256, seed=0, rate=None, nv_choices=(8, 16, 24, 32), steps=100,
+                     kinds=("sod1d", "box2d")):
+    """Request descriptors drawn uniformly from `kinds`: 1-D shock tube with
+    32..512 elements, 2-D periodic box with 16^2..64^2 elements, and (when
+    listed) 2-D Couette channel with 16^2..64^2 elements, wall speed in
+    [0.05, 0.3] and wall temperature in [0.8, 1.2]; p in {1,2,3}; N_1d from
     nv_choices; Kn log-uniform in [1e-4, 1]; perturbation amplitude in
     [0.01, 0.2]. Arrival times are Poisson with the given rate (all at 0 when
     rate is None)."""
@@ -183,7 +186,7 @@ def serving_requests(n=256, seed=0, rate=None, nv_choices=(8, 16, 24, 32), steps
     out = []
     t = 0.0
     for r in range(n):
-        kind = "sod1d" if rng.integers(0, 2) == 0 else "box2d"
+        kind = kinds[int(rng.integers(0, len(kinds)))]
         order = int(rng.integers(1, 4))
         nv1 = int(rng.choice(nv_choices))
         kn = float(10.0 ** rng.uniform(-4.0, 0.0))
@@ -193,10 +196,19 @@ def serving_requests(n=256, seed=0, rate=None, nv_choices=(8, 16, 24, 32), steps
             pb = sod1d(nelem=ne, order=order, nv1=nv1, kn=kn)
             prim_args = {"amp": amp, "k": int(rng.integers(1, 5)),
                          "phase": float(rng.uniform(0, 2 * math.pi))}
-        else:
+        elif kind == "box2d":
             ne1 = int(rng.integers(16, 65))
             pb = box2d(n=ne1, order=order, nv1=nv1, kn=kn)
             prim_args = {"amp": amp}
+        elif kind == "channel2d":
+            ne1 = int(rng.integers(16, 65))
+            pb = channel2d(nx=ne1, ny=ne1, order=order, nv1=nv1, kn=kn,
+                           uw=float(rng.uniform(0.05, 0.3)),
+                           theta_w=float(rng.uniform(0.8, 1.2)))
+            prim_args = {"amp": amp, "k": int(rng.integers(1, 5)),
+                         "phase": float(rng.uniform(0, 2 * math.pi))}
+        else:
+            raise ValueError(kind)
         if rate:
             t += float(rng_t.exponential(1.0 / rate))
         out.append({"id": r, "kind": kind, "problem": pb, "prim_args": prim_args,

@@ -88,14 +88,18 @@ def test_batch_failure_is_isolated(torch):
 
 
 def test_request_loop_completes_mix(torch):
+    """Shock tubes, periodic boxes and Couette channels (diffuse walls) arriving
+    as a Poisson stream all complete."""
     from paper_2308_06196_amd import serve
     _say("serve-mix")
-    descs = wl.serving_requests(n=12, seed=1, rate=200.0, nv_choices=(8, 16), steps=10)
+    descs = wl.serving_requests(n=15, seed=1, rate=200.0, nv_choices=(8, 16), steps=10,
+                                kinds=("sod1d", "box2d", "channel2d"))
+    assert {d["kind"] for d in descs} == {"sod1d", "box2d", "channel2d"}
     for d in descs:  # keep the test small
         pb = d["problem"]
         if pb["dim"] == 2:
-            d["problem"] = wl.box2d(n=min(pb["nelem"][0], 12), order=pb["order"],
-                                    nv1=pb["nvel"][0], kn=pb["mu_ref"])
+            n = min(pb["nelem"][0], 12)
+            pb["nelem"] = [n, n, 1]
     reqs = serve.make_requests(descs)
     ex = serve.BatchExecutor(max_members=8)
     m = serve.Server(ex, capacity_bytes=8 << 30, max_members=8, quantum=4).run(reqs)
