@@ -98,7 +98,12 @@ typedef enum { BGK_HOST = 0, BGK_DEVICE = 1 } bgk_where;
  *   nvel, vlo, vhi   velocity grid (see conventions).
  *   mu_ref, theta_ref, omega
  *                    viscosity law mu = mu_ref (theta/theta_ref)^omega and
- *                    tau = mu/P; mu_ref <= 0 turns the collision term off.
+ *                    tau = mu/P (Sec. 2); mu_ref <= 0 turns the collision
+ *                    term off.
+ *   sutherland       > 0 selects Sutherland's law instead of the power law:
+ *                    mu = mu_ref (theta/theta_ref)^{3/2} (theta_ref + S) /
+ *                    (theta + S) with S = sutherland (temperature units of
+ *                    theta); omega is then ignored.
  *   gamma            ratio of specific heats; <= 0 selects 5/3 (monatomic,
  *                    three velocity components).
  *   precision        bgk_precision.
@@ -125,6 +130,7 @@ typedef struct {
   int32_t equilibrium;
   double wall_theta[3][2];
   double wall_vel[3][2][3];
+  double sutherland;
 } bgk_problem;
 
 /* Counters accumulated on the device since the last state installation. */

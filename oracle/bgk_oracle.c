@@ -28,7 +28,9 @@
  * the documented problem statement, never through code):
  *   - the Maxwellian normalisation uses the velocity dimension m = 3;
  *   - gamma defaults to (m+2)/m = 5/3 (monatomic gas);
- *   - mu = mu_ref (theta/theta_ref)^omega; mu_ref <= 0 switches collisions off;
+ *   - mu = mu_ref (theta/theta_ref)^omega, or Sutherland's law
+ *     mu_ref (theta/theta_ref)^{3/2} (theta_ref + S)/(theta + S) when a
+ *     constant S > 0 is given; mu_ref <= 0 switches collisions off;
  *   - Newton starts from the continuous Maxwellian of Q, stops once the
  *     scaled moment residual is <= tol, then takes one final polishing step;
  *     a step that would make alpha_4 >= 0 is halved until alpha_4 < 0;
@@ -64,6 +66,7 @@ typedef struct {
   int32_t equilibrium;      /* 0 discretely conservative, 1 continuous Maxwellian */
   double wall_theta[3][2];  /* diffuse wall temperature */
   double wall_vel[3][2][3]; /* diffuse wall velocity */
+  double sutherland;        /* > 0: Sutherland constant S (else power law) */
 } orc_problem;
 
 typedef struct {
@@ -450,7 +453,13 @@ static void node_tau(const orc_problem* pr, const orc_ops* op, const double* Q, 
   double UU = (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]) / (rho * rho);
   double P = (op->gamma - 1.0) * (Q[4] - 0.5 * rho * UU);
   double th = P / rho;
-  double mu = pr->mu_ref * pow(th / pr->theta_ref, pr->omega);
+  double mu;
+  if (pr->sutherland > 0.0) { /* Sutherland's law */
+    double S = pr->sutherland;
+    mu = pr->mu_ref * pow(th / pr->theta_ref, 1.5) * (pr->theta_ref + S) / (th + S);
+  } else { /* power law */
+    mu = pr->mu_ref * pow(th / pr->theta_ref, pr->omega);
+  }
   *tau = mu / P;
 }
 

@@ -52,6 +52,7 @@ class _Problem(C.Structure):
         ("equilibrium", C.c_int32),
         ("wall_theta", (C.c_double * 2) * 3),
         ("wall_vel", ((C.c_double * 3) * 2) * 3),
+        ("sutherland", C.c_double),
     ]
 
 
@@ -94,6 +95,7 @@ class Problem:
     equilibrium: int = 0
     wall_theta: tuple = ((1.0, 1.0), (1.0, 1.0), (1.0, 1.0))
     wall_vel: tuple = (((0.0,) * 3,) * 2,) * 3
+    sutherland: float = 0.0
 
     def cstruct(self) -> _Problem:
         s = _Problem()
@@ -110,6 +112,7 @@ class Problem:
         s.mu_ref, s.theta_ref, s.omega, s.gamma = self.mu_ref, self.theta_ref, self.omega, self.gamma
         s.limiter, s.newton_maxit, s.newton_tol = self.limiter, self.newton_maxit, self.newton_tol
         s.equilibrium = int(self.equilibrium)
+        s.sutherland = float(self.sutherland)
         for k in range(3):
             for side in range(2):
                 s.wall_theta[k][side] = float(self.wall_theta[k][side])

@@ -47,6 +47,7 @@ class Problem(C.Structure):
         ("equilibrium", C.c_int32),
         ("wall_theta", (C.c_double * 2) * 3),
         ("wall_vel", ((C.c_double * 3) * 2) * 3),
+        ("sutherland", C.c_double),
     ]
 
 
@@ -83,6 +84,7 @@ def problem_struct(pb: dict, precision: int = FP64) -> Problem:
     s.precision, s.limiter = int(precision), int(pb["limiter"])
     s.newton_maxit, s.newton_tol = int(pb["newton_maxit"]), float(pb["newton_tol"])
     s.equilibrium = int(pb.get("equilibrium", 0))
+    s.sutherland = float(pb.get("sutherland", 0.0))
     wt = pb.get("wall_theta", [(1.0, 1.0)] * 3)
     wv = pb.get("wall_vel", [((0.0,) * 3,) * 2] * 3)
     for k in range(3):

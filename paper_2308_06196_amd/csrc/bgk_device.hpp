@@ -106,6 +106,7 @@ struct NewtonArgs {
   double* Q;   // optional [nx][5] output of the reduced moments
   unsigned long long* diag;
   double gamma, mu_ref, theta_ref, omega, tol;
+  double sutherland;  // > 0: Sutherland constant (power law otherwise)
   int32_t maxit, collide, etab_f32;
   int32_t continuous;  // 1: continuous Maxwellian of (rho, U, theta), no Newton solve
 };

@@ -254,7 +254,10 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
     off += N;
   }
   if (r == 0 && active) {
-    const double mu = A.mu_ref * pow(th / A.theta_ref, A.omega);
+    const double tr = th / A.theta_ref;
+    const double mu = A.sutherland > 0.0
+                          ? A.mu_ref * tr * sqrt(tr) * (A.theta_ref + A.sutherland) / (th + A.sutherland)
+                          : A.mu_ref * pow(tr, A.omega);
     const double tau = mu / P;
 #pragma unroll
     for (int a = 0; a < 5; ++a) out[a] = al[a];

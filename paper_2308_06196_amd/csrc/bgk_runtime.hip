@@ -224,6 +224,8 @@ bgk_status validate(const bgk_problem* pb) {
   }
   if (!(pb->theta_ref > 0.0) && pb->mu_ref > 0.0)
     return fail(BGK_ERR_INVALID_ARG, "theta_ref must be > 0");
+  if (!(pb->sutherland >= 0.0) || !isfinite(pb->sutherland))
+    return fail(BGK_ERR_INVALID_ARG, "sutherland must be finite and >= 0");
   return BGK_OK;
 }
 
@@ -364,6 +366,7 @@ NewtonArgs newton_args(const bgk_solver* s) {
   N.mu_ref = s->pb.mu_ref;
   N.theta_ref = s->pb.theta_ref;
   N.omega = s->pb.omega;
+  N.sutherland = s->pb.sutherland;
   N.tol = s->pb.newton_tol > 0.0 ? s->pb.newton_tol : 1e-14;
   N.maxit = s->pb.newton_maxit > 0 ? s->pb.newton_maxit : 20;
   N.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
@@ -956,7 +959,10 @@ bgk_status bgk_stable_dt(bgk_solver* s, double cfl, double* dt) {
       const double UU = (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / (rho * rho);
       const double P = (s->gamma - 1.0) * (q[4] - 0.5 * rho * UU);
       const double th = P / rho;
-      const double tau = s->pb.mu_ref * pow(th / s->pb.theta_ref, s->pb.omega) / P;
+      const double tr = th / s->pb.theta_ref, S = s->pb.sutherland;
+      const double mu = S > 0.0 ? s->pb.mu_ref * tr * sqrt(tr) * (s->pb.theta_ref + S) / (th + S)
+                                : s->pb.mu_ref * pow(tr, s->pb.omega);
+      const double tau = mu / P;
       tmin = std::min(tmin, tau);
     }
     delete[] Qh;

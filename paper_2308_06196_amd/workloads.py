@@ -46,7 +46,7 @@ def problem(dim, order, nelem, xlo, xhi, nvel, vlo, vhi, kn, bc=None, limiter=1)
         "nvel": list(nvel), "vlo": list(vlo), "vhi": list(vhi),
         "mu_ref": float(kn), "theta_ref": 1.0, "omega": 0.0, "gamma": 0.0,
         "limiter": limiter, "newton_maxit": 20, "newton_tol": 1e-14,
-        "equilibrium": 0,
+        "equilibrium": 0, "sutherland": 0.0,
         "wall_theta": [(1.0, 1.0)] * 3, "wall_vel": [((0.0,) * 3,) * 2] * 3,
     }
 

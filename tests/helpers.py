@@ -5,7 +5,7 @@ from oracle import oracle as orc
 
 KEYS = ["dim", "order", "nelem", "xlo", "xhi", "nvel", "vlo", "vhi", "bc", "mu_ref",
         "theta_ref", "omega", "gamma", "limiter", "newton_maxit", "newton_tol"]
-OPTIONAL = ["equilibrium", "wall_theta", "wall_vel"]
+OPTIONAL = ["equilibrium", "wall_theta", "wall_vel", "sutherland"]
 
 
 def oracle_problem(pb) -> orc.Problem:

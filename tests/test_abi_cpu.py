@@ -36,6 +36,8 @@ def test_status_strings():
     (lambda p: p.update(vlo=[-5.0, -6.0, -6.0]), 1),   # specular needs symmetric grid
     (lambda p: p.update(limiter=3), 1),
     (lambda p: p.update(equilibrium=2), 1),
+    (lambda p: p.update(sutherland=-1.0), 1),
+    (lambda p: p.update(bc=[(2, 2), (0, 0), (0, 0)], wall_theta=[(0.0, 1.0)] * 3), 1),
 ])
 def test_footprint_validation(mutate, status):
     pb = wl.sod1d()
@@ -115,3 +117,11 @@ def test_ablation_node_weights_integrate_exactly(pb):
         lo, hi = pb["xlo"][k], pb["xhi"][k]
         exact = vol / (hi - lo) * (hi ** 3 - lo ** 3) / 3.0
         assert abs(W @ x[:, k] ** 2 - exact) < 1e-12 * abs(exact)
+
+
+def test_diffuse_walls_rejected_on_hexahedra():
+    pb = wl.tgv3d(n=2, order=1, nv1=4)
+    pb["bc"] = [(0, 0), (0, 0), (2, 2)]
+    with pytest.raises(bgk.BGKError) as ei:
+        bgk.footprint(pb)
+    assert ei.value.status == 2

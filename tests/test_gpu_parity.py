@@ -380,3 +380,24 @@ def test_diffuse_walls_match_oracle(torch, name):
     s32.set_state(dev(torch, f0))
     s32.rk3_step(dt, 3)
     assert rel_max(s32.get_state().cpu().numpy(), f_orc) < 1e-5
+
+
+@pytest.mark.parametrize("law", [{"omega": 0.81, "theta_ref": 0.8},
+                                 {"sutherland": 0.4, "theta_ref": 0.8}])
+@pytest.mark.parametrize("name", ["d1p2_sod_spec", "d2p2_box"])
+def test_viscosity_laws_match_oracle(torch, name, law):
+    """Power law with omega != 0 and Sutherland's law: residual and RK3 steps."""
+    pb, kind = CASES[name]
+    pb = dict(pb, **law)
+    _say("viscosity", name, law)
+    err, _ = _residual_case(torch, pb, kind, seed=31)
+    assert err < 1e-12, err
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, kind, seed=32, amp=0.2)
+    dt = orc.stable_dt(pr, f0, 0.1)
+    s = solver(pb)
+    s.set_state(dev(torch, f0))
+    assert abs(s.stable_dt(0.1) - dt) <= 1e-14 * dt
+    s.rk3_step(dt, 3)
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 3)
+    assert rel_max(s.get_state().cpu().numpy(), f_orc) < 1e-12

@@ -452,3 +452,54 @@ def test_diffuse_walls_drag_the_gas():
     t1 = _totals(pr, f1)
     assert abs(t1[1]) < 1e-13 * t1[0]
     assert t1[4] < t0[4] * (1 - 1e-4)
+
+
+# --------------------------------------------------------------------------
+# Viscosity laws (Sec. 2: tau = mu / P)
+# --------------------------------------------------------------------------
+
+def _homogeneous_step(law):
+    pr = P(nelem=(1,), order=1, nvel=(16,) * 3, vlo=(-6.0,) * 3, vhi=(6.0,) * 3, mu_ref=2e-3,
+           limiter=0, theta_ref=0.8, **law)
+    prim = np.tile([1.0, 0.1, 0.0, -0.05, 1.1], (pr.nx, 1))
+    f0 = orc.maxwellian(pr, prim) * wl.perturbation(11, (1, 1, pr.nv), 0.3)
+    return pr, f0
+
+
+@pytest.mark.parametrize("law", [dict(omega=0.81), dict(sutherland=0.4), dict(sutherland=0.4,
+                                                                            omega=0.3)])
+def test_viscosity_law_homogeneous_relaxation(law):
+    """Spatially uniform gas: one SSP-RK3 step relaxes f towards the (fixed)
+    equilibrium with the closed-form factor R(-dt/tau), tau from the chosen law."""
+    pr, f0 = _homogeneous_step(law)
+    Q = orc.moments(pr, f0)[0]
+    Pp = (2.0 / 3.0) * (Q[4] - 0.5 * Q[1:4] @ Q[1:4] / Q[0])
+    th, tr = Pp / Q[0], Pp / Q[0] / pr.theta_ref
+    if pr.sutherland > 0:
+        mu = pr.mu_ref * tr ** 1.5 * (pr.theta_ref + pr.sutherland) / (th + pr.sutherland)
+    else:
+        mu = pr.mu_ref * tr ** pr.omega
+    tau = mu / Pp
+    u, w = orc.velocity_grid(pr)
+    psi = np.column_stack([np.ones(len(u)), u, 0.5 * (u * u).sum(1)])
+    _, a0, _, _ = orc.newton_node(pr, Q)
+    g = np.exp(psi @ _dual_alpha(u, w, Q, a0 * (1 + 1e-4)))
+    dt = 1.3 * tau
+    f1, _ = orc.rk3_step(pr, f0, dt, 1)
+    z = -dt / tau
+    R = 1 + z + z * z / 2 + z ** 3 / 6
+    assert np.abs(f1[0, 0] - g - R * (f0[0, 0] - g)).max() / np.abs(f0).max() < 1e-12
+
+
+def test_sutherland_equals_power_law_at_reference_temperature():
+    """Both laws give mu = mu_ref at theta = theta_ref, so the collision terms agree."""
+    kw = dict(nelem=(1,), order=0, nvel=(12,) * 3, vlo=(-6.0,) * 3, vhi=(6.0,) * 3,
+              theta_ref=0.9)
+    f = orc.maxwellian(P(**kw), np.array([[1.0, 0.0, 0.0, 0.0, 0.9]]))
+    f = f * wl.perturbation(3, f.shape, 0.05)
+    Q = orc.moments(P(**kw), f)[0]
+    th = (2.0 / 3.0) * (Q[4] - 0.5 * Q[1:4] @ Q[1:4] / Q[0]) / Q[0]
+    kw["theta_ref"] = th  # exactly the gas temperature
+    c_pow, _ = orc.collision(P(omega=0.7, **kw), f)
+    c_sut, _ = orc.collision(P(sutherland=0.5, **kw), f)
+    assert np.abs(c_pow - c_sut).max() <= 1e-14 * np.abs(c_pow).max()
