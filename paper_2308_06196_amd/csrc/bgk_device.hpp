@@ -400,8 +400,9 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
-  // the upwind neighbours' nodes of every axis are loaded up front when they
-  // fit the register budget (1-D and 2-D elements); 3-D loads them per axis
+  // the upwind neighbours' nodes are held in registers, one axis at a time,
+  // when they fit the register budget (1-D and 2-D elements); otherwise each
+  // value is read where it is used
   constexpr bool kPreload = NS * DIM <= 48;
   __shared__ double red[red_lds_doubles<NS>()];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -471,10 +472,13 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     src[k] = fin + src_e * NS * nv + src_j;
   }
 
-  // Issue the global loads before any use: the element's equilibrium rows
-  // (factors and 1/tau, first batch), own nodes, the upwind neighbours'
-  // nodes, f^n. Every lane loads (clamped index, no branch): a conditional load
-  // makes the compiler wait for it right there, ahead of the bulk loads.
+  // Global loads in three batches, each issued before any of its values is
+  // used: (1) the element's equilibrium rows (factors and 1/tau, first
+  // batch), own nodes and the axis-0 upwind neighbour's nodes; (2) the next
+  // axis' neighbour after the axis-0 transport (its registers are then free:
+  // 142 instead of 213 VGPRs at p = 3 in FP64, three waves per SIMD); (3) f^n
+  // after the transport. Every lane loads (clamped index, no branch): a
+  // conditional load makes the compiler wait for it right there.
   constexpr int kU = 8;
   const int ntab = NS * S;
   const ST* et = (const ST*)A.etab + node0 * S;
@@ -493,17 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
   if constexpr (kPreload) {
 #pragma unroll
-    for (int k = 0; k < DIM; ++k)
-#pragma unroll
-      for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][(int64_t)i * nv];
-  }
-  // f^n last: it is needed only by the final combine, so the transport can
-  // start while it is still in flight
-  CT fnv[NS];
-  if constexpr (MODE == 0) {
-    const ST* fn = (const ST*)A.fn + node0 * nv + jj;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[(int64_t)i * nv];
+    for (int i = 0; i < NS; ++i) nbv[0][i] = (CT)src[0][(int64_t)i * nv];
   }
   // equilibrium rows (NS x S) of this element -> LDS
   if (A.collide) {
@@ -523,6 +517,13 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     int S1 = 1;
 #pragma unroll
     for (int m = 0; m < k; ++m) S1 *= N1;
+    if constexpr (kPreload) {
+      if (k > 0) {  // batch (2): keep the scheduler from hoisting these loads
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][(int64_t)i * nv];
+      }
+    }
     const CT a = (CT)(vel.u[k] * g.scale[k]);
     CT lown[N1], lext[N1], Gin[N1];
 #pragma unroll
@@ -588,6 +589,13 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     }
   }
 
+  // f^n: needed only by the final combine, in flight during the relaxation
+  CT fnv[NS];
+  if constexpr (MODE == 0) {
+    const ST* fn = (const ST*)A.fn + node0 * nv + jj;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[(int64_t)i * nv];
+  }
   // BGK relaxation towards the discretely conservative equilibrium,
   // g = Ex[bx] Ey[by] Ez[bz] from the LDS factors
   CT L[NS];
