@@ -143,8 +143,8 @@ def cpu_baseline(pb_full, prim_fn, budget_s=12.0):
                       f"direct velocity sums"}
 
 
-def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4,
-            kinds=("sod1d", "box2d")):
+def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
+            kinds=("sod1d", "box2d"), policy="sjf"):
     """Serving mix (shock tubes and periodic boxes, p in 1..3, 8^3..32^3 velocities,
     Kn log-uniform [1e-4, 1], 100 steps each). A saturating run (all requests at
     t = 0) measures the capacity; then the same requests arrive as a Poisson
@@ -161,7 +161,8 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4,
 
     def batched(rate):
         ex = serve.BatchExecutor(max_members=max_members)
-        m = serve.Server(ex, pool, max_members=max_members, quantum=quantum).run(reqs(rate))
+        m = serve.Server(ex, pool, max_members=max_members, quantum=quantum,
+                         policy=policy).run(reqs(rate))
         ex.close()
         return m
 
@@ -171,6 +172,7 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=64, quantum=4,
     seq_sat = serve.run_sequential(reqs(None))
     seq_pois = serve.run_sequential(reqs(0.8 * cap_rate))
     return {"requests": n_requests, "steps_each": steps, "kinds": list(kinds),
+            "policy": policy, "max_members": max_members,
             "total_dof": int(sum(r.dof for r in reqs(None))),
             "capacity_requests_per_s": cap_rate, "poisson_rate_per_s": 0.8 * cap_rate,
             "batched_saturating": sat, "batched_poisson": pois,
@@ -190,6 +192,10 @@ def main():
     ap.add_argument("--serving", type=int, default=24, metavar="N",
                     help="requests in the serving mix (0: skip)")
     ap.add_argument("--serving-steps", type=int, default=100)
+    ap.add_argument("--serving-policy", default="sjf", choices=["fifo", "sjf"],
+                    help="admission order of the batched server")
+    ap.add_argument("--serving-members", type=int, default=8,
+                    help="requests resident in the batch at once")
     ap.add_argument("--serving-kinds", default="sod1d,box2d",
                     help="request kinds of the serving mix (sod1d, box2d, channel2d)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -231,7 +237,8 @@ def main():
         line["mixed"] = {"dtype": "f32-bulk/f64-collision", "value": mx["value"],
                          "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps)}
     if a.serving:
-        sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")))
+        sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")),
+                     policy=a.serving_policy, max_members=a.serving_members)
         line["serving"] = sv
         p, q = sv["batched_poisson"], sv["sequential_fp64_poisson"]
         print(f"[bench] serving {a.serving} requests: batched p50 {p['p50_s']:.3f} s, p99 "

@@ -125,3 +125,26 @@ def test_metrics_percentiles():
     assert m["p50_s"] == pytest.approx(2.5)
     assert m["p99_s"] == pytest.approx(np.percentile([1, 2, 3, 4], 99))
     assert m["dof_updates_per_s"] == pytest.approx(40 / 4.0)
+
+
+def test_sjf_admits_least_work_first():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    reqs = _requests(n=16, rate=None, seed=4)  # all arrive at t = 0
+    serve.Server(ex, 10 ** 15, max_members=1, quantum=5, clock=clk, sleep=clk.sleep,
+                 policy="sjf").run(reqs)
+    work = {r.id: r.dof * r.steps for r in reqs}
+    order = [work[i] for i in ex.order]
+    assert order == sorted(order)
+
+
+def test_sjf_lowers_median_latency_under_saturation():
+    res = {}
+    for policy in ("fifo", "sjf"):
+        clk = Clock()
+        ex = FakeExecutor(clk)
+        reqs = _requests(n=24, rate=None, seed=6)
+        res[policy] = serve.Server(ex, 10 ** 15, max_members=2, quantum=5, clock=clk,
+                                   sleep=clk.sleep, policy=policy).run(reqs)
+    assert res["sjf"]["p50_s"] < res["fifo"]["p50_s"]
+    assert res["sjf"]["completed"] == res["fifo"]["completed"] == 24
