@@ -132,49 +132,12 @@ __device__ __forceinline__ int64_t work_element(const int32_t* order, int64_t e0
 }
 
 // ---------------------------------------------------------------------------
-// Work-group reduction of per-lane FP64 values (fixed order, no atomics).
-//
-// A butterfly reduce-scatter over the 64 lanes: at the level of lane bit o,
-// lanes with the bit clear keep the lower half of their values and lanes
-// with it set keep the upper half, each adding the partner's copy of the
-// kept half. Partners: bits 5 and 4 via gfx950's v_permlane32_swap /
-// v_permlane16_swap (swap the odd 32-/16-lane rows of the first operand
-// with the even rows of the second, which needs no select); bit 3 via DPP
-// row_ror:8 (lane ^ 8 inside a 16-lane row); bit 2 via row_half_mirror
-// (lane -> 7 - lane inside 8 lanes, which pairs the two halves); bits 1 and
-// 0 via quad_perm. Odd counts are all-reduced on that bit instead.
+// Cross-lane partners for fixed-order FP64 reductions: lane bits 5 and 4 via
+// gfx950's v_permlane32_swap / v_permlane16_swap (swap the odd 32-/16-lane
+// rows of the first operand with the even rows of the second), lower bits via
+// DPP (row_ror:8 for lane ^ 8, row_half_mirror to pair the halves of 8 lanes,
+// quad_perm for bits 1 and 0).
 // ---------------------------------------------------------------------------
-constexpr int shuffle_cost(int m) {
-  int c = 0;
-  for (int o = 32; o >= 1; o >>= 1) {
-    if ((m & 1) == 0) {
-      m >>= 1;
-      c += m;
-    } else {
-      c += m;
-    }
-  }
-  return c;
-}
-// nodes per reduction group: the largest divisor of NS not above 8
-constexpr int group_of(int ns) {
-  int g = 1;
-  for (int d = 1; d <= 8 && d <= ns; ++d)
-    if (ns % d == 0) g = d;
-  return g;
-}
-constexpr int best_pad(int m) {
-  int best = m, bc = shuffle_cost(m);
-  for (int k = 1; k <= 64; k <<= 1) {
-    int mp = (m + k - 1) / k * k;
-    if (shuffle_cost(mp) < bc) {
-      bc = shuffle_cost(mp);
-      best = mp;
-    }
-  }
-  return best;
-}
-
 template <int O>
 __device__ __forceinline__ double swap_sum(double x, double y) {
   const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
@@ -197,51 +160,6 @@ __device__ __forceinline__ double dpp_partner(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
-}
-
-// One level per template instance (each level owns a fresh, statically
-// indexed array, which keeps every value in registers).
-template <int H, int STEP>
-__device__ __forceinline__ void wave_level(const double (&v)[H], double* lds_wave, int lane,
-                                           int base, int dup) {
-  if constexpr (STEP == 6) {
-    if ((lane & dup) == 0) {
-#pragma unroll
-      for (int q = 0; q < H; ++q) lds_wave[base + q] = v[q];
-    }
-  } else {
-    constexpr int O = 32 >> STEP;
-    if constexpr (H % 2 == 0) {
-      constexpr int HH = H / 2;
-      const bool up = (lane & O) != 0;
-      double w[HH];
-      if constexpr (O == 32 || O == 16) {
-#pragma unroll
-        for (int q = 0; q < HH; ++q) w[q] = swap_sum<O>(v[q], v[q + HH]);
-      } else {
-#pragma unroll
-        for (int q = 0; q < HH; ++q) {
-          const double send = up ? v[q] : v[q + HH];
-          const double keep = up ? v[q + HH] : v[q];
-          w[q] = keep + dpp_partner<O>(send);
-        }
-      }
-      wave_level<HH, STEP + 1>(w, lds_wave, lane, base + (up ? HH : 0), dup);
-    } else {
-      double w[H];
-      if constexpr (O == 32) {
-#pragma unroll
-        for (int q = 0; q < H; ++q) w[q] = v[q] + __shfl_xor(v[q], 32, 64);
-      } else if constexpr (O == 16) {
-#pragma unroll
-        for (int q = 0; q < H; ++q) w[q] = v[q] + __shfl_xor(v[q], 16, 64);
-      } else {
-#pragma unroll
-        for (int q = 0; q < H; ++q) w[q] = v[q] + dpp_partner<O>(v[q]);
-      }
-      wave_level<H, STEP + 1>(w, lds_wave, lane, base, dup | O);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -323,52 +241,6 @@ __device__ __forceinline__ const DevOpsT<CT>& ops_of(const StageArgs& A) {
   else return A.opf;
 }
 
-// LDS doubles needed by the moment reduction of one element.
-template <int NS>
-constexpr int red_lds_doubles() {
-  return (kBlock / 64) * (NS / group_of(NS)) * best_pad(5 * group_of(NS));
-}
-
-// Moment partials of one element's NS node values (per lane), written for
-// this work-group's velocity chunk into partials[(node)*nchunk + chunk][5].
-// Lanes outside the velocity grid must enter with w = 0. Contains one
-// work-group barrier.
-template <int NS, typename CT>
-__device__ __forceinline__ void element_partials(const CT (&fv)[NS], const Vel& vel,
-                                                 double* __restrict__ partials, int64_t node0,
-                                                 int nchunk, int chunk, double* red) {
-  constexpr int G = group_of(NS);
-  constexpr int NG = NS / G;
-  constexpr int M = 5 * G;
-  constexpr int MP = best_pad(M);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
-#pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    double v[MP];
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      const double wf = vel.w * (double)fv[gi * G + q];
-      v[5 * q + 0] = wf;
-      v[5 * q + 1] = wf * vel.u[0];
-      v[5 * q + 2] = wf * vel.u[1];
-      v[5 * q + 3] = wf * vel.u[2];
-      v[5 * q + 4] = wf * psi4;
-    }
-#pragma unroll
-    for (int q = M; q < MP; ++q) v[q] = 0.0;
-    wave_level<MP, 0>(v, red + (wave * NG + gi) * MP, lane, 0, 0);
-  }
-  lds_barrier();
-  for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
-    const int gi = t / M, idx = t - gi * M;
-    double s = red[gi * MP + idx];
-#pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) s += red[(w * NG + gi) * MP + idx];
-    partials[((node0 + t / 5) * nchunk + chunk) * 5 + (t % 5)] = s;
-  }
-}
-
 // Equilibrium rows from index kU * kBlock on (the first kU * kBlock entries
 // are loaded with the bulk loads) -> LDS.
 template <int kU, typename ST, typename CT>
@@ -388,6 +260,79 @@ __device__ __forceinline__ void table_rest(CT* tab, const ST* et, int ntab) {
   }
 }
 
+// Moment partials of one element as an FP64 matrix product on the matrix
+// cores: per wave, P[node][m] = sum over the wave's 64 velocities v of
+// f[node][v] * (w psi_m)(v), i.e. a 16 x 64 by 64 x 5 contraction done as 16
+// v_mfma_f64_16x16x4f64 steps (4 velocities each; nodes padded to 16 rows,
+// moments to 16 columns). The operands need velocity across the K index, so
+// each lane first writes its column (its velocity's node values, and w psi of
+// its velocity) to LDS and reads back the A (f) and B (w psi) entries of its
+// MFMA lane: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the result
+// D[i][j] lands in lane j + 16 (i % 4), register i / 4. The four waves' tiles
+// are then added in a fixed order. `stage` is the work-group's MFMA staging
+// area (mfma_lds_bytes<ST>() bytes), `red` 4 x 16 x 5 doubles.
+constexpr int kGst = 66;  // LDS row stride (elements) of the staged node values
+template <typename ST>
+constexpr int mfma_lds_bytes() {
+  return (kBlock / 64) * (64 * 5 * (int)sizeof(double) + 16 * kGst * (int)sizeof(ST));
+}
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int NS, typename ST, typename CT>
+__device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const Vel& vel,
+                                                      double* __restrict__ partials,
+                                                      int64_t node0, int nchunk, int chunk,
+                                                      unsigned char* stage, double* red) {
+  static_assert(NS <= 16, "the nodes of an element fill at most one 16-row tile");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* ps = reinterpret_cast<double*>(stage) + wave * 64 * 5;
+  ST* gw = reinterpret_cast<ST*>(stage + (kBlock / 64) * 64 * 5 * sizeof(double)) + wave * 16 * kGst;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) gw[i * kGst + lane] = (ST)fv[i];
+  const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
+  ps[lane * 5 + 0] = vel.w;
+  ps[lane * 5 + 1] = vel.w * vel.u[0];
+  ps[lane * 5 + 2] = vel.w * vel.u[1];
+  ps[lane * 5 + 3] = vel.w * vel.u[2];
+  ps[lane * 5 + 4] = vel.w * psi4;
+  // the lanes of this wave read what the others wrote (LDS is ordered within
+  // a wave; the fences keep the compiler from moving the reads up)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  const int r = lane & 15, k = lane >> 4;  // row / column index, K index (lane group)
+  mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  // operands of 8 steps are read before the first of them is used, so the
+  // LDS latency is paid twice per wave instead of 16 times
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    double a[8], b[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int v = 4 * (8 * half + st) + k;
+      a[st] = r < NS ? (double)gw[r * kGst + v] : 0.0;
+      b[st] = r < 5 ? ps[v * 5 + r] : 0.0;
+    }
+#pragma unroll
+    for (int st = 0; st < 8; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc, 0, 0, 0);
+  }
+  if (r < 5) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int node = 4 * q + k;
+      if (node < NS) red[(wave * 16 + node) * 5 + r] = acc[q];
+    }
+  }
+  lds_barrier();
+  for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
+    const int node = t / 5, m = t - node * 5;
+    double sum = red[node * 5 + m];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) sum += red[(w * 16 + node) * 5 + m];
+    partials[((node0 + node) * nchunk + chunk) * 5 + m] = sum;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stage kernel: FR transport (volume + upwind inflow-face lift) + BGK
 // relaxation + SSP-RK combine + positivity limiter + next-stage moment
@@ -404,7 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   // when they fit the register budget (1-D and 2-D elements); otherwise each
   // value is read where it is used
   constexpr bool kPreload = NS * DIM <= 48;
-  __shared__ double red[red_lds_doubles<NS>()];
+  __shared__ double red[(kBlock / 64) * 16 * 5];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
@@ -659,8 +604,11 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) oe[(int64_t)i * nv] = (ST)o[i];
     }
-    // moment partials of what was stored (FP64 sums)
-    element_partials<NS, CT>(o, vel, A.partials, node0, g.nchunk, chunk, red);
+    // moment partials of what was stored (FP64 sums on the matrix cores); the
+    // staging area reuses the equilibrium rows' LDS once every wave is done
+    // with them
+    if (A.collide) lds_barrier();
+    element_partials_mfma<NS, ST, CT>(o, vel, A.partials, node0, g.nchunk, chunk, dyn_lds, red);
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
   }
 }
@@ -671,7 +619,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
-  __shared__ double red[red_lds_doubles<NS>()];
+  __shared__ double red[(kBlock / 64) * 16 * 5];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];  // MFMA staging
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
@@ -686,7 +635,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   CT f[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
-  element_partials<NS, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, red);
+  element_partials_mfma<NS, ST, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, dyn_lds, red);
 }
 
 }  // namespace bgk

@@ -412,7 +412,10 @@ template <typename ST>
 static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   const dim3 grid((unsigned)(A.g.nchunk * A.ecount)), block(kBlock);
   const int key = A.g.dim * 10 + (A.g.n1 - 1);
-  const size_t lds = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(ST) : 0;
+  // dynamic LDS: equilibrium rows (relaxation), then, in the 1-D/2-D
+  // kernels, the MFMA staging of the moment partials in the same bytes
+  const size_t tab = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(ST) : 0;
+  const size_t lds = A.g.dim < 3 && mode != 1 ? std::max(tab, (size_t)mfma_lds_bytes<ST>()) : tab;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
     if (mode == 0 && A.a != 0.0)                                           \
@@ -422,7 +425,7 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
     else if (mode == 1)                                                    \
       hipLaunchKernelGGL((k_stage<D, P, ST, 1>), grid, block, lds, s, A);  \
     else                                                                   \
-      hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, 0, s, A);     \
+      hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, lds, s, A);   \
     break;
 #define BGK_CASE3(P)                                                       \
   case 30 + P:                                                             \
