@@ -4,8 +4,9 @@
 // Data layout in HBM (one solver):
 //   f[elem][node][vel]   storage precision, velocity fastest (coalesced rows
 //                        of nv values per spatial node)
-//   partials[node][chunk][5]  FP64 moment partial sums of one stage output,
-//                        one entry per 256-wide velocity chunk
+//   partials[chunk][node][5]  FP64 moment partial sums of one stage output,
+//                        one entry per velocity chunk of a work-group (chunk
+//                        major, so a work-group writes one contiguous block)
 //   params[node][8]      FP64 (alpha_0..alpha_4, 1/tau, tau, status) of the
 //                        discretely conservative equilibrium
 //   etab[node][S]        one-dimensional factors of that equilibrium and
@@ -129,28 +130,6 @@ __device__ __forceinline__ int64_t work_element(const int32_t* order, int64_t e0
                                                 int64_t ecount) {
   const int64_t k = w % ecount;
   return order ? (int64_t)order[k] : e0 + k;
-}
-
-// ---------------------------------------------------------------------------
-// Cross-lane partners for fixed-order FP64 reductions: lane bits 5 and 4 via
-// gfx950's v_permlane32_swap / v_permlane16_swap (swap the odd 32-/16-lane
-// rows of the first operand with the even rows of the second), lower bits via
-// DPP (row_ror:8 for lane ^ 8, row_half_mirror to pair the halves of 8 lanes,
-// quad_perm for bits 1 and 0).
-// ---------------------------------------------------------------------------
-template <int O>
-__device__ __forceinline__ double swap_sum(double x, double y) {
-  const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
-  const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
-  if constexpr (O == 32) {
-    const auto rl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
-    const auto rh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
-    return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
-  } else {
-    const auto rl = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
-    const auto rh = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
-    return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
-  }
 }
 
 // Partner value across lane bit O (O <= 8) by a DPP move (all source lanes valid).
@@ -281,7 +260,7 @@ typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 template <int NS, typename ST, typename CT>
 __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const Vel& vel,
                                                       double* __restrict__ partials,
-                                                      int64_t node0, int nchunk, int chunk,
+                                                      int64_t node0, int64_t nx, int chunk,
                                                       unsigned char* stage, double* red) {
   static_assert(NS <= 16, "the nodes of an element fill at most one 16-row tile");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -329,7 +308,7 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
     double sum = red[node * 5 + m];
 #pragma unroll
     for (int w = 1; w < kBlock / 64; ++w) sum += red[(w * 16 + node) * 5 + m];
-    partials[((node0 + node) * nchunk + chunk) * 5 + m] = sum;
+    partials[((int64_t)chunk * nx + node0 + node) * 5 + m] = sum;
   }
 }
 
@@ -608,7 +587,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     // staging area reuses the equilibrium rows' LDS once every wave is done
     // with them
     if (A.collide) lds_barrier();
-    element_partials_mfma<NS, ST, CT>(o, vel, A.partials, node0, g.nchunk, chunk, dyn_lds, red);
+    element_partials_mfma<NS, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, dyn_lds, red);
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
   }
 }
@@ -635,7 +614,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   CT f[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
-  element_partials_mfma<NS, ST, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, dyn_lds, red);
+  element_partials_mfma<NS, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, dyn_lds, red);
 }
 
 }  // namespace bgk

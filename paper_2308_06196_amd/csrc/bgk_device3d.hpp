@@ -65,94 +65,79 @@ __device__ __forceinline__ T group_allmin(T x) {
   return x;
 }
 
-// Butterfly reduce-scatter over lane bits 5, 4, 3 only (partners keep the
-// low three lane bits, which hold the plane index): afterwards lanes that
-// differ only in bits 3..5 hold disjoint index ranges of their partial sums.
-template <int H, int STEP, int W>
-__device__ __forceinline__ void wave_level_hi(const double (&v)[H], double* lds_wave, int lane,
-                                              int base) {
-  if constexpr (STEP == 3) {
-    // lane keeps H values for indices base..base+H-1; slot (width W) by its
-    // low three lane bits
-#pragma unroll
-    for (int q = 0; q < H; ++q) lds_wave[(lane & 7) * W + base + q] = v[q];
-  } else {
-    constexpr int O = 32 >> STEP;
-    static_assert(H % 2 == 0, "reduction count must halve three times");
-    constexpr int HH = H / 2;
-    const bool up = (lane & O) != 0;
-    double w[HH];
-    if constexpr (O == 32 || O == 16) {
-#pragma unroll
-      for (int q = 0; q < HH; ++q) w[q] = swap_sum<O>(v[q], v[q + HH]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < HH; ++q) {
-        const double send = up ? v[q] : v[q + HH];
-        const double keep = up ? v[q + HH] : v[q];
-        w[q] = keep + dpp_partner<8>(send);
-      }
-    }
-    wave_level_hi<HH, STEP + 1, W>(w, lds_wave, lane, base + (up ? HH : 0));
-  }
+// Moment partials of one element on the matrix cores (FP64 MFMA), as in the
+// 1-D/2-D kernels: per wave and per plane pl, P[q][m] = sum over the wave's
+// 64 / G velocities v of f[pl][q][v] (w psi_m)(v), a (p+1)^2 x K by K x 5
+// contraction done in K / 4 v_mfma_f64_16x16x4f64 steps (A[i][k] in lane
+// i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), register
+// i / 4). Every lane stages its plane's values, the first lane of each
+// velocity group stages w psi of that velocity; the four waves' results are
+// added in a fixed order. `stage` is mfma3_lds_bytes<P, ST>() bytes, `red`
+// 4 x NS x 5 doubles.
+template <int P, typename ST>
+constexpr int mfma3_lds_bytes() {
+  constexpr int G = Plane3<P>::G, K = 64 / G, RS = K + 2;
+  return (kBlock / 64) * (K * 5 * (int)sizeof(double) + G * 16 * RS * (int)sizeof(ST));
 }
 
-// Moment partials of the lane's plane values (P2 nodes), velocity-chunk sums
-// into partials[(node)*nchunk + chunk][5]. Lanes outside the grid (or idle
-// planes) enter with w = 0. LDS: 4 waves x 8 low-lane slots x 64 doubles.
-template <int P>
-struct PlaneRed {
-  static constexpr int P2 = Plane3<P>::P2;
-  static constexpr int GN = P2 % 8 == 0 ? 8 : P2;  // nodes per reduction group
-  static constexpr int NGR = P2 / GN;
-  static constexpr int M = 5 * GN;
-  static constexpr int MP = (M + 7) / 8 * 8;         // halves three times
-  static constexpr int LDS = (kBlock / 64) * NGR * 8 * MP;
-};
-
-template <int P, typename CT>
-__device__ __forceinline__ void plane_partials(const CT (&fv)[Plane3<P>::P2], const Vel& vel,
-                                               double* __restrict__ partials, int64_t node0,
-                                               int nchunk, int chunk, int plane, double* red) {
+template <int P, typename ST, typename CT>
+__device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2], const Vel& vel,
+                                                    double* __restrict__ partials, int64_t node0,
+                                                    int64_t nx, int chunk, int lp,
+                                                    unsigned char* stage, double* red) {
   using PL = Plane3<P>;
-  constexpr int P2 = PL::P2;
-  constexpr int G = PL::G;
-  using R = PlaneRed<P>;
-  constexpr int GN = R::GN, NGR = R::NGR, M = R::M, MP = R::MP;
+  constexpr int N1 = PL::N1, G = PL::G, P2 = PL::P2, NS = PL::NS;
+  constexpr int K = 64 / G, RS = K + 2;
+  static_assert(P2 <= 16, "the nodes of a plane fill at most one 16-row tile");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
+  const int vw = lane / G;  // velocity of this lane inside the wave
+  double* ps = reinterpret_cast<double*>(stage) + wave * K * 5;
+  ST* gw = reinterpret_cast<ST*>(stage + (kBlock / 64) * K * 5 * sizeof(double)) +
+           wave * G * 16 * RS;
+  if (lp < N1) {
 #pragma unroll
-  for (int gi = 0; gi < NGR; ++gi) {
-    double v[MP];
+    for (int q = 0; q < P2; ++q) gw[(lp * 16 + q) * RS + vw] = (ST)fv[q];
+  }
+  if (lp == 0) {
+    const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
+    ps[vw * 5 + 0] = vel.w;
+    ps[vw * 5 + 1] = vel.w * vel.u[0];
+    ps[vw * 5 + 2] = vel.w * vel.u[1];
+    ps[vw * 5 + 3] = vel.w * vel.u[2];
+    ps[vw * 5 + 4] = vel.w * psi4;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  const int r = lane & 15, k = lane >> 4;
 #pragma unroll
-    for (int q = 0; q < GN; ++q) {
-      const double wf = vel.w * (double)fv[gi * GN + q];
-      v[5 * q + 0] = wf;
-      v[5 * q + 1] = wf * vel.u[0];
-      v[5 * q + 2] = wf * vel.u[1];
-      v[5 * q + 3] = wf * vel.u[2];
-      v[5 * q + 4] = wf * psi4;
+  for (int pl = 0; pl < N1; ++pl) {
+    double a[K / 4], b[K / 4];
+#pragma unroll
+    for (int st = 0; st < K / 4; ++st) {
+      const int v = 4 * st + k;
+      a[st] = r < P2 ? (double)gw[(pl * 16 + r) * RS + v] : 0.0;
+      b[st] = r < 5 ? ps[v * 5 + r] : 0.0;
     }
+    mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = M; q < MP; ++q) v[q] = 0.0;
-    wave_level_hi<MP, 0, MP>(v, red + (wave * NGR + gi) * 8 * MP, lane, 0);
+    for (int st = 0; st < K / 4; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc, 0, 0, 0);
+    if (r < 5) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int node = 4 * q + k;
+        if (node < P2) red[(wave * NS + pl * P2 + node) * 5 + r] = acc[q];
+      }
+    }
   }
   lds_barrier();
-  // final sums: for each plane, node of the plane and moment, add the
-  // 4 waves x (8 / G) low-lane slots that hold that plane
-  constexpr int NOUT = PL::N1 * P2 * 5;
-  for (int t = threadIdx.x; t < NOUT; t += kBlock) {
-    const int pl = t / (P2 * 5), rest = t - pl * P2 * 5;
-    const int qn = rest / 5, m = rest - qn * 5;
-    const int gi = qn / GN, idx = (qn - gi * GN) * 5 + m;
-    double s = 0.0;
+  for (int t = threadIdx.x; t < NS * 5; t += kBlock) {
+    const int node = t / 5, m = t - node * 5;
+    double sum = red[node * 5 + m];
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w)
-#pragma unroll
-      for (int hi = 0; hi < 8 / G; ++hi) s += red[((w * NGR + gi) * 8 + hi * G + pl) * MP + idx];
-    partials[((node0 + pl * P2 + qn) * nchunk + chunk) * 5 + m] = s;
+    for (int w = 1; w < kBlock / 64; ++w) sum += red[(w * NS + node) * 5 + m];
+    partials[((int64_t)chunk * nx + node0 + node) * 5 + m] = sum;
   }
-  (void)plane;
 }
 
 
@@ -161,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
   constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
-  __shared__ double red[PlaneRed<P>::LDS];
+  __shared__ double red[(kBlock / 64) * NS * 5];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
@@ -404,7 +389,10 @@ __global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
 #pragma unroll
       for (int q = 0; q < P2; ++q) oe[(int64_t)q * nv] = (ST)o[q];
     }
-    plane_partials<P, CT>(o, vel, A.partials, node0, g.nchunk, chunk, lp, red);
+    // moment partials on the matrix cores; the staging area reuses the
+    // equilibrium rows' LDS once every wave is done with them
+    if (A.collide) lds_barrier();
+    plane_partials_mfma<P, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, lp, dyn_lds, red);
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
   }
 }
@@ -414,7 +402,8 @@ __global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
   constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
-  __shared__ double red[PlaneRed<P>::LDS];
+  __shared__ double red[(kBlock / 64) * NS * 5];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];  // MFMA staging
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
@@ -432,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
   CT f[P2];
 #pragma unroll
   for (int q = 0; q < P2; ++q) f[q] = (CT)fe[(int64_t)q * nv];
-  plane_partials<P, CT>(f, vel, A.partials, e * NS, g.nchunk, chunk, lp, red);
+  plane_partials_mfma<P, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, lp, dyn_lds, red);
 }
 
 }  // namespace bgk

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   const bool active = node_raw < g.nx;
   const int64_t node = active ? node_raw : g.nx - 1;
   double Q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const double* pp = A.partials + node * g.nchunk * 5;
+  const double* pp = A.partials + node * 5;  // chunk c at pp[c * nx * 5]
   // chunk partials: batches of 4 chunks per lane, all loads of a batch in flight
   for (int c0 = 0; c0 < g.nchunk; c0 += 4 * kTeam) {
     double v[4][5];
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
     for (int u = 0; u < 4; ++u) {
       const int c = c0 + u * kTeam + r;
 #pragma unroll
-      for (int m = 0; m < 5; ++m) v[u][m] = c < g.nchunk ? pp[c * 5 + m] : 0.0;
+      for (int m = 0; m < 5; ++m) v[u][m] = c < g.nchunk ? pp[(int64_t)c * g.nx * 5 + m] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -286,10 +286,10 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const 
   const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= g.nx) return;
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const double* pp = partials + node * g.nchunk * 5;
+  const double* pp = partials + node * 5;
   for (int c = 0; c < g.nchunk; ++c)
 #pragma unroll
-    for (int m = 0; m < 5; ++m) q[m] += pp[c * 5 + m];
+    for (int m = 0; m < 5; ++m) q[m] += pp[(int64_t)c * g.nx * 5 + m];
 #pragma unroll
   for (int m = 0; m < 5; ++m) Q[node * 5 + m] = q[m];
 }
@@ -415,7 +415,7 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   // dynamic LDS: equilibrium rows (relaxation), then, in the 1-D/2-D
   // kernels, the MFMA staging of the moment partials in the same bytes
   const size_t tab = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(ST) : 0;
-  const size_t lds = A.g.dim < 3 && mode != 1 ? std::max(tab, (size_t)mfma_lds_bytes<ST>()) : tab;
+  const size_t lds = mode != 1 ? std::max(tab, (size_t)mfma_lds_bytes<ST>()) : tab;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
     if (mode == 0 && A.a != 0.0)                                           \
@@ -428,16 +428,19 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
       hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, lds, s, A);   \
     break;
 #define BGK_CASE3(P)                                                       \
-  case 30 + P:                                                             \
+  case 30 + P: {                                                           \
+    const size_t lds3 =                                                    \
+        mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
     if (mode == 0 && A.a != 0.0)                                           \
-      hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds, s, A);    \
+      hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds3, s, A);   \
     else if (mode == 0)                                                    \
-      hipLaunchKernelGGL((k_stage3<P, ST, 3>), grid, block, lds, s, A);    \
+      hipLaunchKernelGGL((k_stage3<P, ST, 3>), grid, block, lds3, s, A);   \
     else if (mode == 1)                                                    \
-      hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds, s, A);    \
+      hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds3, s, A);   \
     else                                                                   \
-      hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, 0, s, A);       \
-    break;
+      hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, lds3, s, A);    \
+    break;                                                                 \
+  }
   switch (key) {
     BGK_CASE(1, 1) BGK_CASE(1, 2) BGK_CASE(1, 3)
     BGK_CASE(2, 1) BGK_CASE(2, 2) BGK_CASE(2, 3)
