@@ -181,6 +181,34 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Face coefficients for the upwind selection, one copy per wave in LDS:
+// row 1 holds (lamL, GL), used where u_k > 0 (inflow through the left face),
+// row 0 holds (lamR, GR). A lane reads its row through a per-lane address;
+// picking between two uniform values per lane in registers would take two
+// moves and a select per 32-bit half (one scalar operand per VALU op).
+template <typename CT>
+struct alignas(16) FaceRows {
+  CT r[2][2 * kMaxN1];
+};
+
+template <typename CT, int N1>
+__device__ __forceinline__ void face_rows_store(FaceRows<CT>& fr, const DevOpsT<CT>& OP) {
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int b = 0; b < N1; ++b) {
+      fr.r[0][b] = OP.lamR[b];
+      fr.r[0][kMaxN1 + b] = OP.GR[b];
+      fr.r[1][b] = OP.lamL[b];
+      fr.r[1][kMaxN1 + b] = OP.GL[b];
+    }
+  }
+  // the other lanes of this wave read what lane 0 wrote (LDS is ordered
+  // within a wave; the fences keep the compiler from moving the reads up)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 __device__ __forceinline__ double sreg(double x) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
@@ -241,21 +269,77 @@ __device__ __forceinline__ void table_rest(CT* tab, const ST* et, int ntab) {
 
 // Moment partials of one element as an FP64 matrix product on the matrix
 // cores: per wave, P[node][m] = sum over the wave's 64 velocities v of
-// f[node][v] * (w psi_m)(v), i.e. a 16 x 64 by 64 x 5 contraction done as 16
-// v_mfma_f64_16x16x4f64 steps (4 velocities each; nodes padded to 16 rows,
-// moments to 16 columns). The operands need velocity across the K index, so
-// each lane first writes its column (its velocity's node values, and w psi of
-// its velocity) to LDS and reads back the A (f) and B (w psi) entries of its
-// MFMA lane: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the result
-// D[i][j] lands in lane j + 16 (i % 4), register i / 4. The four waves' tiles
-// are then added in a fixed order. `stage` is the work-group's MFMA staging
-// area (mfma_lds_bytes<ST>() bytes), `red` 4 x 16 x 5 doubles.
+// f[node][v] * (w psi_m)(v), a 16 x 64 by 64 x 5 contraction. The operands
+// need velocity across the K index, so each lane first writes its column (its
+// velocity's node values, and w psi of its velocity) to LDS; wave_moments_4x4
+// reads the operands back and runs the products. The four waves' tiles are
+// then added in a fixed order. `stage` is the work-group's MFMA staging area
+// (mfma_lds_bytes<ST>() bytes), `red` 4 x 16 x 5 doubles.
 constexpr int kGst = 66;  // LDS row stride (elements) of the staged node values
 template <typename ST>
 constexpr int mfma_lds_bytes() {
   return (kBlock / 64) * (64 * 5 * (int)sizeof(double) + 16 * kGst * (int)sizeof(ST));
 }
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+// Moment sums of the values one wave staged in LDS:
+//   redw[n][m] = sum_{v < K} F[n][v] W[v][m],  m < 5,
+// with F in rows of `gw` (row stride rs; NT tiles of 16 rows of which the
+// first NV are used, node n = t NV + r for row 16 t + r) and W in `ps`
+// ([v][5], FP64). On v_mfma_f64_4x4x4_4b, block b of one instruction takes
+// four rows (nodes) and four moments for four velocities; the energy moment
+// takes a second instruction with the same A operand. Operand layout of
+// block b: A[i][k] in lane 16k + 4b + i, B[k][j] in lane 16k + 4b + j; the
+// result D[i][j] lands in lane 16i + 4b + j. (FP64 MFMA has the FP64 vector
+// rate here, so the 16x16x4 shape, with 11 of its 16 columns idle for five
+// moments, would take twice the matrix-core cycles.)
+template <int NT, int NV, int K, typename ST>
+__device__ __forceinline__ void wave_moments_4x4(const ST* gw, int rs, const double* ps,
+                                                 double* redw) {
+  static_assert(NV <= 16 && K % 4 == 0, "tiles of 16 rows, velocities in fours");
+  const int lane = threadIdx.x & 63;
+  const int k = lane >> 4, blk = (lane >> 2) & 3, j = lane & 3;
+  const int ra = 4 * blk + j;  // A row of this lane inside a tile
+  double d0[NT], d1[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) d0[t] = d1[t] = 0.0;
+  // operands of up to 8 steps are read before the first of them is used
+  // (B once per batch, A one tile at a time)
+  constexpr int kB = K / 4 < 8 ? K / 4 : 8;
+#pragma unroll
+  for (int s0 = 0; s0 < K / 4; s0 += kB) {
+    double b0[kB], b1[kB];
+#pragma unroll
+    for (int st = 0; st < kB; ++st) {
+      const int v = 4 * (s0 + st) + k;
+      b0[st] = ps[v * 5 + j];
+      b1[st] = j == 0 ? ps[v * 5 + 4] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double a[kB];
+#pragma unroll
+      for (int st = 0; st < kB; ++st) {
+        const int v = 4 * (s0 + st) + k;
+        a[st] = ra < NV ? (double)gw[(16 * t + ra) * rs + v] : 0.0;
+      }
+#pragma unroll
+      for (int st = 0; st < kB; ++st) {
+        d0[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[st], b0[st], d0[t], 0, 0, 0);
+        d1[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[st], b1[st], d1[t], 0, 0, 0);
+      }
+    }
+  }
+  const int rd = 4 * blk + k;  // result row of this lane inside a tile
+  if (rd < NV) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double* o = redw + (t * NV + rd) * 5;
+      o[j] = d0[t];
+      if (j == 0) o[4] = d1[t];
+    }
+  }
+}
 
 template <int NS, typename ST, typename CT>
 __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const Vel& vel,
@@ -279,29 +363,7 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  const int r = lane & 15, k = lane >> 4;  // row / column index, K index (lane group)
-  mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  // operands of 8 steps are read before the first of them is used, so the
-  // LDS latency is paid twice per wave instead of 16 times
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    double a[8], b[8];
-#pragma unroll
-    for (int st = 0; st < 8; ++st) {
-      const int v = 4 * (8 * half + st) + k;
-      a[st] = r < NS ? (double)gw[r * kGst + v] : 0.0;
-      b[st] = r < 5 ? ps[v * 5 + r] : 0.0;
-    }
-#pragma unroll
-    for (int st = 0; st < 8; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc, 0, 0, 0);
-  }
-  if (r < 5) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int node = 4 * q + k;
-      if (node < NS) red[(wave * 16 + node) * 5 + r] = acc[q];
-    }
-  }
+  wave_moments_4x4<1, NS, 64, ST>(gw, kGst, ps, red + wave * 16 * 5);
   lds_barrier();
   for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
     const int node = t / 5, m = t - node * 5;
@@ -320,7 +382,9 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
 // (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
 // ---------------------------------------------------------------------------
 template <int DIM, int P, typename ST, int MODE>
-__global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 3 : 4)))
+    k_stage(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
@@ -329,11 +393,14 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
   // value is read where it is used
   constexpr bool kPreload = NS * DIM <= 48;
   __shared__ double red[(kBlock / 64) * 16 * 5];
+  __shared__ FaceRows<CT> frows[kBlock / 64];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
   const DevGeom& g = A.g;
   const DevOpsT<CT>& OP = ops_of<CT>(A);
+  FaceRows<CT>& fr = frows[threadIdx.x >> 6];
+  face_rows_store<CT, N1>(fr, OP);
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
@@ -450,13 +517,15 @@ __global__ void __launch_bounds__(kBlock) k_stage(const StageArgs A) {
     }
     const CT a = (CT)(vel.u[k] * g.scale[k]);
     CT lown[N1], lext[N1], Gin[N1];
+    {
+      const CT* ro = fr.r[pos[k] ? 1 : 0];
+      const CT* re = fr.r[use_right[k] ? 0 : 1];
 #pragma unroll
-    for (int bb = 0; bb < N1; ++bb) {
-      const CT lL = sreg(OP.lamL[bb]), lR = sreg(OP.lamR[bb]);
-      const CT gL = sreg(OP.GL[bb]), gR = sreg(OP.GR[bb]);
-      lown[bb] = pos[k] ? lL : lR;
-      lext[bb] = use_right[k] ? lR : lL;
-      Gin[bb] = pos[k] ? gL : gR;
+      for (int bb = 0; bb < N1; ++bb) {
+        lown[bb] = ro[bb];
+        Gin[bb] = ro[kMaxN1 + bb];
+        lext[bb] = re[bb];
+      }
     }
     // diffuse walls of this axis touching the element (uniform)
     const double* rho_lo = nullptr;

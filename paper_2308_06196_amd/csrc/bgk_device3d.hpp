@@ -68,9 +68,8 @@ __device__ __forceinline__ T group_allmin(T x) {
 // Moment partials of one element on the matrix cores (FP64 MFMA), as in the
 // 1-D/2-D kernels: per wave and per plane pl, P[q][m] = sum over the wave's
 // 64 / G velocities v of f[pl][q][v] (w psi_m)(v), a (p+1)^2 x K by K x 5
-// contraction done in K / 4 v_mfma_f64_16x16x4f64 steps (A[i][k] in lane
-// i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), register
-// i / 4). Every lane stages its plane's values, the first lane of each
+// contraction on the matrix cores (wave_moments_4x4, one 16-row tile per
+// plane). Every lane stages its plane's values, the first lane of each
 // velocity group stages w psi of that velocity; the four waves' results are
 // added in a fixed order. `stage` is mfma3_lds_bytes<P, ST>() bytes, `red`
 // 4 x NS x 5 doubles.
@@ -109,27 +108,7 @@ __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  const int r = lane & 15, k = lane >> 4;
-#pragma unroll
-  for (int pl = 0; pl < N1; ++pl) {
-    double a[K / 4], b[K / 4];
-#pragma unroll
-    for (int st = 0; st < K / 4; ++st) {
-      const int v = 4 * st + k;
-      a[st] = r < P2 ? (double)gw[(pl * 16 + r) * RS + v] : 0.0;
-      b[st] = r < 5 ? ps[v * 5 + r] : 0.0;
-    }
-    mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int st = 0; st < K / 4; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc, 0, 0, 0);
-    if (r < 5) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int node = 4 * q + k;
-        if (node < P2) red[(wave * NS + pl * P2 + node) * 5 + r] = acc[q];
-      }
-    }
-  }
+  wave_moments_4x4<N1, P2, K, ST>(gw, RS, ps, red + wave * NS * 5);
   lds_barrier();
   for (int t = threadIdx.x; t < NS * 5; t += kBlock) {
     const int node = t / 5, m = t - node * 5;
@@ -142,7 +121,9 @@ __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2
 
 
 template <int P, typename ST, int MODE>
-__global__ void __launch_bounds__(kBlock) k_stage3(const StageArgs A) {
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 1 : 3)))
+    k_stage3(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
   constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
