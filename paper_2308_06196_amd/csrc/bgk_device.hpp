@@ -43,10 +43,23 @@ struct DevGeom {
   int32_t nv1[3];
   int32_t tabw;  // S = nv1[0] + nv1[1] + nv1[2] + 1 (factors, then 1/tau)
   int64_t ne, nx, nv;
+  int64_t nvb;  // velocity blocks of kVB per element (internal layout)
   int32_t nchunk;
   double vlo[3], du[3];
   double scale[3];  // 2 / h_k
 };
+
+// Internal state layout: f[element][velocity block][node][kVB], blocks of
+// kVB consecutive velocities (the last one padded). The values one wave reads
+// for one node are kVB consecutive entries and the nodes of an element are kVB
+// entries apart, so a wave streams one contiguous block per element and node
+// offsets fit in the load instructions. Offset of (element e, node a of the
+// element, velocity j).
+constexpr int kVB = 64;
+__host__ __device__ __forceinline__ int64_t f_offset(const DevGeom& g, int64_t e, int a,
+                                                     int64_t j) {
+  return ((e * g.nvb + j / kVB) * g.ns + a) * kVB + j % kVB;
+}
 
 template <typename T>
 struct DevOpsT {
@@ -460,7 +473,7 @@ __global__ void __launch_bounds__(kBlock)
       src_e = e + (int64_t)(nk - ek[k]) * stride;
     }
     use_right[k] = (pos[k] != wall);
-    src[k] = fin + src_e * NS * nv + src_j;
+    src[k] = fin + f_offset(g, src_e, 0, src_j);
   }
 
   // Global loads in three batches, each issued before any of its values is
@@ -481,14 +494,14 @@ __global__ void __launch_bounds__(kBlock)
       tv[u] = et[t < ntab ? t : ntab - 1];
     }
   }
-  const ST* fe = fin + node0 * nv + jj;
+  const ST* fe = fin + f_offset(g, e, 0, jj);
   CT f[NS];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
+  for (int i = 0; i < NS; ++i) f[i] = (CT)fe[i * kVB];
   CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
   if constexpr (kPreload) {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) nbv[0][i] = (CT)src[0][(int64_t)i * nv];
+    for (int i = 0; i < NS; ++i) nbv[0][i] = (CT)src[0][i * kVB];
   }
   // equilibrium rows (NS x S) of this element -> LDS
   if (A.collide) {
@@ -512,7 +525,7 @@ __global__ void __launch_bounds__(kBlock)
       if (k > 0) {  // batch (2): keep the scheduler from hoisting these loads
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][(int64_t)i * nv];
+        for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][i * kVB];
       }
     }
     const CT a = (CT)(vel.u[k] * g.scale[k]);
@@ -562,7 +575,7 @@ __global__ void __launch_bounds__(kBlock)
         if constexpr (kPreload)
           xv = nbv[k][base + bb * S1];
         else
-          xv = (CT)src[k][(int64_t)(base + bb * S1) * nv];
+          xv = (CT)src[k][(base + bb * S1) * kVB];
         ext += lext[bb] * xv;
       }
       if (dwall) {  // uniform: the element touches a diffuse wall of axis k
@@ -585,9 +598,9 @@ __global__ void __launch_bounds__(kBlock)
   // f^n: needed only by the final combine, in flight during the relaxation
   CT fnv[NS];
   if constexpr (MODE == 0) {
-    const ST* fn = (const ST*)A.fn + node0 * nv + jj;
+    const ST* fn = (const ST*)A.fn + f_offset(g, e, 0, jj);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[(int64_t)i * nv];
+    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[i * kVB];
   }
   // BGK relaxation towards the discretely conservative equilibrium,
   // g = Ex[bx] Ey[by] Ez[bz] from the LDS factors
@@ -648,9 +661,9 @@ __global__ void __launch_bounds__(kBlock)
     }
     ST* out = (ST*)A.out;
     if (valid) {
-      ST* oe = out + node0 * nv + j;
+      ST* oe = out + f_offset(g, e, 0, j);
 #pragma unroll
-      for (int i = 0; i < NS; ++i) oe[(int64_t)i * nv] = (ST)o[i];
+      for (int i = 0; i < NS; ++i) oe[i * kVB] = (ST)o[i];
     }
     // moment partials of what was stored (FP64 sums on the matrix cores); the
     // staging area reuses the equilibrium rows' LDS once every wave is done
@@ -679,10 +692,10 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   const int jj = valid ? j : (int)nv - 1;
   Vel vel = velocity_of(g, jj);
   if (!valid) vel.w = 0.0;
-  const ST* fe = (const ST*)A.fin + e * NS * nv + jj;
+  const ST* fe = (const ST*)A.fin + f_offset(g, e, 0, jj);
   CT f[NS];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) f[i] = (CT)fe[(int64_t)i * nv];
+  for (int i = 0; i < NS; ++i) f[i] = (CT)fe[i * kVB];
   element_partials_mfma<NS, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, dyn_lds, red);
 }
 

@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kBlock)
       src_e = e + (int64_t)(nk - ek[k]) * stride;
     }
     use_right[k] = (pos[k] != wall);
-    src[k] = fin + (src_e * NS + pl * P2) * nv + src_j;
+    src[k] = fin + f_offset(g, src_e, pl * P2, src_j);
   }
 
   // loads: equilibrium rows (first batch), own plane, the x-, y- and
@@ -201,20 +201,20 @@ __global__ void __launch_bounds__(kBlock)
       tv[u] = et[t < ntab ? t : ntab - 1];
     }
   }
-  const ST* fe = fin + (node0 + pl * P2) * nv + jj;
+  const ST* fe = fin + f_offset(g, e, pl * P2, jj);
   CT f[P2];
 #pragma unroll
-  for (int q = 0; q < P2; ++q) f[q] = (CT)fe[(int64_t)q * nv];
+  for (int q = 0; q < P2; ++q) f[q] = (CT)fe[q * kVB];
   CT nb[3][P2];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][(int64_t)q * nv];
+    for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][q * kVB];
   CT fnv[P2];  // last: needed only by the final combine
   if constexpr (MODE == 0) {
-    const ST* fn = (const ST*)A.fn + (node0 + pl * P2) * nv + jj;
+    const ST* fn = (const ST*)A.fn + f_offset(g, e, pl * P2, jj);
 #pragma unroll
-    for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[(int64_t)q * nv];
+    for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[q * kVB];
   }
 
   if (A.collide) {
@@ -366,9 +366,9 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
     if (act) {
-      ST* oe = (ST*)A.out + (node0 + pl * P2) * nv + j;
+      ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);
 #pragma unroll
-      for (int q = 0; q < P2; ++q) oe[(int64_t)q * nv] = (ST)o[q];
+      for (int q = 0; q < P2; ++q) oe[q * kVB] = (ST)o[q];
     }
     // moment partials on the matrix cores; the staging area reuses the
     // equilibrium rows' LDS once every wave is done with them
@@ -398,10 +398,10 @@ __global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
   const int jj = valid ? j : (int)nv - 1;
   Vel vel = velocity_of(g, jj);
   if (!(valid && live)) vel.w = 0.0;
-  const ST* fe = (const ST*)A.fin + (e * NS + pl * P2) * nv + jj;
+  const ST* fe = (const ST*)A.fin + f_offset(g, e, pl * P2, jj);
   CT f[P2];
 #pragma unroll
-  for (int q = 0; q < P2; ++q) f[q] = (CT)fe[(int64_t)q * nv];
+  for (int q = 0; q < P2; ++q) f[q] = (CT)fe[q * kVB];
   plane_partials_mfma<P, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, lp, dyn_lds, red);
 }
 

@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
   const bool outgoing = valid && (side == 0 ? a < 0.0 : a > 0.0);
   const double wt = outgoing ? vel.w * fabs(a) : 0.0;
   const int S1 = k == 0 ? 1 : N1;
-  const ST* fe = (const ST*)W.fin + e * NS * nv + jj;
+  const ST* fe = (const ST*)W.fin + f_offset(g, e, 0, jj);
   double v[NF];
 #pragma unroll
   for (int fp = 0; fp < NF; ++fp) {
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
     double tr = 0.0;
 #pragma unroll
     for (int bb = 0; bb < N1; ++bb)
-      tr += (side == 0 ? W.lamL[bb] : W.lamR[bb]) * (double)fe[(int64_t)(base + bb * S1) * nv];
+      tr += (side == 0 ? W.lamL[bb] : W.lamR[bb]) * (double)fe[(base + bb * S1) * kVB];
     v[fp] = wt * tr;
   }
 #pragma unroll
@@ -392,15 +392,32 @@ __global__ void __launch_bounds__(kBlock) k_maxwellian(const DevGeom g, const do
     const double rho = q[0], th = q[4];
     const double nrm = rho / pow(2.0 * M_PI * th, 1.5);
     const double dx = v.u[0] - q[1], dy = v.u[1] - q[2], dz = v.u[2] - q[3];
-    f[node * g.nv + j] = (ST)(nrm * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * th)));
+    f[f_offset(g, node / g.ns, (int)(node % g.ns), j)] =
+        (ST)(nrm * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * th)));
   }
 }
 
-template <typename SRC, typename DST>
-__global__ void __launch_bounds__(256) k_convert(const SRC* in, DST* out, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    out[i] = (DST)in[i];
+// Exchange between the canonical FP64 layout f[elem][node][vel] and the
+// internal layout in storage precision: entries i0 .. i0+m-1 of the canonical
+// array, held at canon[0 .. m-1] (a staging window or the whole array).
+template <typename DST>
+__global__ void __launch_bounds__(256) k_to_internal(const DevGeom g, const double* canon, DST* f,
+                                                     int64_t i0, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, per_e = (int64_t)g.ns * g.nv;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
+    const int64_t i = i0 + t, e = i / per_e, r = i - e * per_e, a = r / g.nv;
+    f[f_offset(g, e, (int)a, r - a * g.nv)] = (DST)canon[t];
+  }
+}
+
+template <typename SRC>
+__global__ void __launch_bounds__(256) k_to_canonical(const DevGeom g, const SRC* f, double* canon,
+                                                      int64_t i0, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, per_e = (int64_t)g.ns * g.nv;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
+    const int64_t i = i0 + t, e = i / per_e, r = i - e * per_e, a = r / g.nv;
+    canon[t] = (double)f[f_offset(g, e, (int)a, r - a * g.nv)];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -513,24 +530,27 @@ hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim
   return hipGetLastError();
 }
 
-hipError_t launch_to_storage(int precision, const double* in, void* out, int64_t n,
-                             hipStream_t s) {
-  const unsigned grid = (unsigned)std::min<int64_t>(grid_of(n, 256), 65536);
-  if (precision == 0) {
-    return hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
-  }
-  hipLaunchKernelGGL((k_convert<double, float>), dim3(grid), dim3(256), 0, s, in, (float*)out, n);
+hipError_t launch_to_storage(int precision, const DevGeom& g, const double* in, void* out,
+                             int64_t i0, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(grid_of(m, 256), 65536);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_to_internal<double>, dim3(grid), dim3(256), 0, s, g, in, (double*)out, i0, m);
+  else
+    hipLaunchKernelGGL(k_to_internal<float>, dim3(grid), dim3(256), 0, s, g, in, (float*)out, i0, m);
   return hipGetLastError();
 }
 
-hipError_t launch_from_storage(int precision, const void* in, double* out, int64_t n,
-                               hipStream_t s) {
-  const unsigned grid = (unsigned)std::min<int64_t>(grid_of(n, 256), 65536);
-  if (precision == 0) {
-    return hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
-  }
-  hipLaunchKernelGGL((k_convert<float, double>), dim3(grid), dim3(256), 0, s, (const float*)in,
-                     out, n);
+hipError_t launch_from_storage(int precision, const DevGeom& g, const void* in, double* out,
+                               int64_t i0, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(grid_of(m, 256), 65536);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_to_canonical<double>, dim3(grid), dim3(256), 0, s, g, (const double*)in,
+                       out, i0, m);
+  else
+    hipLaunchKernelGGL(k_to_canonical<float>, dim3(grid), dim3(256), 0, s, g, (const float*)in,
+                       out, i0, m);
   return hipGetLastError();
 }
 

@@ -25,9 +25,9 @@ hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, doub
                                   hipStream_t s);
 hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,
                              hipStream_t s);
-hipError_t launch_to_storage(int precision, const double* in, void* out, int64_t n,
-                             hipStream_t s);
-hipError_t launch_from_storage(int precision, const void* in, double* out, int64_t n,
-                               hipStream_t s);
+hipError_t launch_to_storage(int precision, const DevGeom& g, const double* in, void* out,
+                             int64_t i0, int64_t m, hipStream_t s);
+hipError_t launch_from_storage(int precision, const DevGeom& g, const void* in, double* out,
+                               int64_t i0, int64_t m, hipStream_t s);
 
 }  // namespace bgk

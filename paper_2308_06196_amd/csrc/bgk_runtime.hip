@@ -160,7 +160,7 @@ void gauss_nodes(int n1, double* xi) {
 
 struct Layout {
   size_t f[3], partials, params, etab, order, Q, prim, diag, wallp, wall_part, wall_rho, total;
-  int64_t nx, nv, ne;
+  int64_t nx, nv, ne, nvb;
   int ns, nchunk;
   int64_t wall_points;  // flux points on diffuse walls
   size_t fbytes;
@@ -240,7 +240,8 @@ Layout layout_of(const bgk_problem* pb) {
   const int vb = velocities_per_block(pb->dim, pb->order);
   L.nchunk = (int)((L.nv + vb - 1) / vb);
   const size_t s = pb->precision == BGK_FP64 ? 8 : 4;
-  L.fbytes = (size_t)L.nx * (size_t)L.nv * s;
+  L.nvb = (L.nv + kVB - 1) / kVB;
+  L.fbytes = (size_t)L.nx * (size_t)(L.nvb * kVB) * s;  // internal layout, padded blocks
   size_t off = 0;
   for (int b = 0; b < 3; ++b) {
     L.f[b] = off;
@@ -521,36 +522,27 @@ bgk_status check_failed(bgk_solver* s) {
   return BGK_OK;
 }
 
-// Copy n FP64 values from host into storage-precision device memory dst,
-// staging through the device scratch region [stage, stage + cap).
+// Install n canonical FP64 values from host into the internal layout at dst
+// (storage precision), staging windows of the canonical array through the
+// device scratch region [stage, stage + cap).
 bgk_status host_to_storage(bgk_solver* s, const double* h, void* dst, int64_t n, char* stage,
                            size_t cap) {
-  if (s->precision == BGK_FP64) {
-    HIP_TRY(hipMemcpyAsync(dst, h, (size_t)n * 8, hipMemcpyHostToDevice, s->stream));
-    return BGK_OK;
-  }
   const int64_t per = (int64_t)(cap / 8);
   for (int64_t o = 0; o < n; o += per) {
     const int64_t m = std::min(per, n - o);
     HIP_TRY(hipMemcpyAsync(stage, h + o, (size_t)m * 8, hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(launch_to_storage(s->precision, (const double*)stage, (char*)dst + o * s->s_bytes(), m,
-                              s->stream));
+    HIP_TRY(launch_to_storage(s->precision, s->g, (const double*)stage, dst, o, m, s->stream));
   }
   return BGK_OK;
 }
 
+// Copy the state at src (internal layout) to n canonical FP64 values on the host.
 bgk_status storage_to_host(bgk_solver* s, const void* src, double* h, int64_t n, char* stage,
                            size_t cap) {
-  if (s->precision == BGK_FP64) {
-    HIP_TRY(hipMemcpyAsync(h, src, (size_t)n * 8, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    return BGK_OK;
-  }
   const int64_t per = (int64_t)(cap / 8);
   for (int64_t o = 0; o < n; o += per) {
     const int64_t m = std::min(per, n - o);
-    HIP_TRY(launch_from_storage(s->precision, (const char*)src + o * s->s_bytes(), (double*)stage,
-                                m, s->stream));
+    HIP_TRY(launch_from_storage(s->precision, s->g, src, (double*)stage, o, m, s->stream));
     HIP_TRY(hipMemcpyAsync(h + o, stage, (size_t)m * 8, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
   }
@@ -653,6 +645,7 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
   g.ne = s->L.ne;
   g.nx = s->L.nx;
   g.nv = s->L.nv;
+  g.nvb = s->L.nvb;
   g.nchunk = s->L.nchunk;
   build_ops(g.n1, g.dim, s->op);
   if (pb->dim == 3) brick_order(g.nelem, s->order_host);
@@ -729,7 +722,7 @@ bgk_status bgk_set_state(bgk_solver* s, const double* f, int32_t where) {
   if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
   const int64_t n = s->L.nx * s->L.nv;
   if (where == BGK_DEVICE) {
-    HIP_TRY(launch_to_storage(s->precision, f, s->f(0), n, s->stream));
+    HIP_TRY(launch_to_storage(s->precision, s->g, f, s->f(0), 0, n, s->stream));
   } else {
     bgk_status st = host_to_storage(s, f, s->f(0), n, (char*)s->f(1), 2 * s->L.fbytes);
     if (st) return st;
@@ -761,7 +754,7 @@ bgk_status bgk_get_state(bgk_solver* s, double* f, int32_t where) {
   if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
   const int64_t n = s->L.nx * s->L.nv;
   if (where == BGK_DEVICE) {
-    HIP_TRY(launch_from_storage(s->precision, s->f(0), f, n, s->stream));
+    HIP_TRY(launch_from_storage(s->precision, s->g, s->f(0), f, 0, n, s->stream));
   } else {
     bgk_status st = storage_to_host(s, s->f(0), f, n, (char*)s->f(1), 2 * s->L.fbytes);
     if (st) return st;
@@ -782,9 +775,9 @@ bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_
   const void* fin = s->f(0);
   if (f_in) {
     if (where == BGK_DEVICE) {
-      HIP_TRY(launch_to_storage(s->precision, f_in, s->f(1), n, s->stream));
+      HIP_TRY(launch_to_storage(s->precision, s->g, f_in, s->f(1), 0, n, s->stream));
     } else {
-      // FP64: f1 holds the input directly; FP32: stage through f2
+      // staged through f2
       bgk_status st = host_to_storage(s, f_in, s->f(1), n, (char*)s->f(2), s->L.fbytes);
       if (st) return st;
     }
