@@ -145,13 +145,30 @@ __device__ __forceinline__ int64_t work_element(const int32_t* order, int64_t e0
   return order ? (int64_t)order[k] : e0 + k;
 }
 
-// Partner value across lane bit O (O <= 8) by a DPP move (all source lanes valid).
-template <int O>
-__device__ __forceinline__ double dpp_partner(double x) {
-  constexpr int ctrl = O == 8 ? 0x128 : O == 4 ? 0x141 : O == 2 ? 0x4E : 0xB1;
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+// DPP moves whose source lanes are all valid (permutations inside a row), so
+// no previous value is needed (bound_ctrl set); the compiler can then fold
+// the move into the consuming add or multiply.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
+}
+
+// Partner value across lane bit O (O <= 8) by a DPP move.
+template <int O, typename T>
+__device__ __forceinline__ T dpp_partner(T x) {
+  return dpp_mov<O == 8 ? 0x128 : O == 4 ? 0x141 : O == 2 ? 0x4E : 0xB1>(x);
+}
+
+// Value of lane (lane ^ R) inside the quad, R < 4.
+template <int R, typename T>
+__device__ __forceinline__ T quad_xor(T x) {
+  return dpp_mov<R == 1 ? 0xB1 : R == 2 ? 0x4E : 0x1B>(x);
 }
 
 // ---------------------------------------------------------------------------
@@ -196,15 +213,17 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Face coefficients for the upwind selection, one copy per wave in LDS:
 // row 1 holds (lamL, GL), used where u_k > 0 (inflow through the left face),
-// row 0 holds (lamR, GR). A lane reads its row through a per-lane address;
+// row 0 holds (lamR, GR); then the derivative matrix, for kernels that need
+// a per-lane row of it. A lane reads its row through a per-lane address;
 // picking between two uniform values per lane in registers would take two
 // moves and a select per 32-bit half (one scalar operand per VALU op).
 template <typename CT>
 struct alignas(16) FaceRows {
   CT r[2][2 * kMaxN1];
+  CT D[kMaxN1 * kMaxN1];  // D[a][b] at a kMaxN1 + b, zero outside the element
 };
 
-template <typename CT, int N1>
+template <typename CT, int N1, bool WITH_D = false>
 __device__ __forceinline__ void face_rows_store(FaceRows<CT>& fr, const DevOpsT<CT>& OP) {
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -213,6 +232,12 @@ __device__ __forceinline__ void face_rows_store(FaceRows<CT>& fr, const DevOpsT<
       fr.r[0][kMaxN1 + b] = OP.GR[b];
       fr.r[1][b] = OP.lamL[b];
       fr.r[1][kMaxN1 + b] = OP.GL[b];
+    }
+    if constexpr (WITH_D) {
+#pragma unroll
+      for (int a = 0; a < kMaxN1; ++a)
+#pragma unroll
+        for (int b = 0; b < kMaxN1; ++b) fr.D[a * kMaxN1 + b] = a < N1 && b < N1 ? OP.D[a][b] : CT(0);
     }
   }
   // the other lanes of this wave read what lane 0 wrote (LDS is ordered

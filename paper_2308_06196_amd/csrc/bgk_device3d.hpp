@@ -23,43 +23,20 @@ template <int P> struct Plane3 {
   static constexpr int NS = N1 * N1 * N1;
 };
 
-// Value of lane b of this lane's group (G = 2 or 4 lanes inside a quad).
-template <int G, int B>
-__device__ __forceinline__ double group_bcast(double x) {
-  constexpr int ctrl = G == 4 ? (B | (B << 2) | (B << 4) | (B << 6))
-                              : (B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6));
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <int G, int B>
-__device__ __forceinline__ float group_bcast(float x) {
-  constexpr int ctrl = G == 4 ? (B | (B << 2) | (B << 4) | (B << 6))
-                              : (B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6));
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
-}
-
 // Sum / min over the G lanes of a group (partners lane ^ 1, lane ^ 2; every
 // lane ends with the same bits).
-template <int G>
-__device__ __forceinline__ double group_allsum(double x) {
-  x += dpp_partner<1>(x);
-  if constexpr (G == 4) x += dpp_partner<2>(x);
-  return x;
-}
-template <int G>
-__device__ __forceinline__ float group_allsum(float x) {
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
-  if constexpr (G == 4)
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+template <int G, typename T>
+__device__ __forceinline__ T group_allsum(T x) {
+  x += quad_xor<1>(x);
+  if constexpr (G == 4) x += quad_xor<2>(x);
   return x;
 }
 template <int G, typename T>
 __device__ __forceinline__ T group_allmin(T x) {
-  T y = (T)dpp_partner<1>((double)x);
+  T y = quad_xor<1>(x);
   x = y < x ? y : x;
   if constexpr (G == 4) {
-    y = (T)dpp_partner<2>((double)x);
+    y = quad_xor<2>(x);
     x = y < x ? y : x;
   }
   return x;
@@ -122,17 +99,20 @@ __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2
 
 template <int P, typename ST, int MODE>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 1 : 3)))
+    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 2 : 3)))
     k_stage3(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
   constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
   __shared__ double red[(kBlock / 64) * NS * 5];
+  __shared__ FaceRows<CT> frows[kBlock / 64];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
 
   const DevGeom& g = A.g;
   const DevOpsT<CT>& OP = ops_of<CT>(A);
+  FaceRows<CT>& fr = frows[threadIdx.x >> 6];
+  face_rows_store<CT, N1, true>(fr, OP);
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
@@ -235,13 +215,15 @@ __global__ void __launch_bounds__(kBlock)
     const int S1 = k == 0 ? 1 : N1;
     const CT a = (CT)(vel.u[k] * g.scale[k]);
     CT lown[N1], lext[N1], Gin[N1];
+    {
+      const CT* ro = fr.r[pos[k] ? 1 : 0];
+      const CT* re = fr.r[use_right[k] ? 0 : 1];
 #pragma unroll
-    for (int bb = 0; bb < N1; ++bb) {
-      const CT lL = sreg(OP.lamL[bb]), lR = sreg(OP.lamR[bb]);
-      const CT gL = sreg(OP.GL[bb]), gR = sreg(OP.GR[bb]);
-      lown[bb] = pos[k] ? lL : lR;
-      lext[bb] = use_right[k] ? lR : lL;
-      Gin[bb] = pos[k] ? gL : gR;
+      for (int bb = 0; bb < N1; ++bb) {
+        lown[bb] = ro[bb];
+        Gin[bb] = ro[kMaxN1 + bb];
+        lext[bb] = re[bb];
+      }
     }
 #pragma unroll
     for (int base = 0; base < P2; ++base) {
@@ -265,40 +247,34 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   }
-  // z: the column of node q is spread over the group's lanes
+  // z: the column of node q is spread over the group's lanes; lane lp holds
+  // plane lp and its partners lane ^ r the other planes. The derivative is
+  // sum_r D[lp][lp ^ r] f(lp ^ r); the trace difference ext - own is one
+  // group sum of lext(lp) f_nb - lown(lp) f (zero weights on idle lanes).
   {
     const CT a = (CT)(vel.u[2] * g.scale[2]);
-    CT lown[N1], Drow[N1];
-    CT lext_mine = (CT)0, gin_mine = (CT)0;
+    const CT* ro = fr.r[pos[2] ? 1 : 0];
+    const CT* re = fr.r[use_right[2] ? 0 : 1];
+    const CT lown_mine = live ? ro[pl] : (CT)0;
+    const CT lext_mine = live ? re[pl] : (CT)0;
+    const CT ag = a * ro[kMaxN1 + pl];
+    CT Dr[G];
 #pragma unroll
-    for (int bb = 0; bb < N1; ++bb) {
-      const CT lL = sreg(OP.lamL[bb]), lR = sreg(OP.lamR[bb]);
-      lown[bb] = pos[2] ? lL : lR;
-      const CT le = use_right[2] ? lR : lL;
-      const CT gl = pos[2] ? sreg(OP.GL[bb]) : sreg(OP.GR[bb]);
-      lext_mine = bb == lp ? le : lext_mine;
-      gin_mine = bb == lp ? gl : gin_mine;
-      CT dr = (CT)0;
-#pragma unroll
-      for (int ia = 0; ia < N1; ++ia) dr = ia == lp ? sreg(OP.D[ia][bb]) : dr;
-      Drow[bb] = dr;
+    for (int r = 0; r < G; ++r) {
+      const int b = lp ^ r;
+      Dr[r] = live && b < N1 ? fr.D[pl * kMaxN1 + b] : (CT)0;
     }
-    if (!live) lext_mine = (CT)0;
 #pragma unroll
     for (int q = 0; q < P2; ++q) {
-      CT col[N1];
-      col[0] = group_bcast<G, 0>(f[q]);
-      if constexpr (N1 > 1) col[1] = group_bcast<G, 1>(f[q]);
-      if constexpr (N1 > 2) col[2] = group_bcast<G, 2>(f[q]);
-      if constexpr (N1 > 3) col[3] = group_bcast<G, 3>(f[q]);
-      CT own = (CT)0, df = (CT)0;
-#pragma unroll
-      for (int bb = 0; bb < N1; ++bb) {
-        own += lown[bb] * col[bb];
-        df += Drow[bb] * col[bb];
+      const CT fq = f[q];
+      CT df = Dr[0] * fq;
+      df += Dr[1] * quad_xor<1>(fq);
+      if constexpr (G == 4) {
+        df += Dr[2] * quad_xor<2>(fq);
+        df += Dr[3] * quad_xor<3>(fq);
       }
-      const CT ext = group_allsum<G>(lext_mine * nb[2][q]);
-      acc[q] += a * df + a * (ext - own) * gin_mine;
+      const CT jl = group_allsum<G>(lext_mine * nb[2][q] - lown_mine * fq);
+      acc[q] += a * df + ag * jl;
     }
   }
 
