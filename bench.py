@@ -7,7 +7,8 @@ p=3, 24^3 velocities on [-6,6]^3, Kn=1e-3; 226,492,416 phase-space DOF), run
 in FP64 and with FP32 bulk storage / FP64 collision side by side.
 
 Prints one JSON line: value = FP64 DOF-updates/s; "mixed" holds the FP32-bulk
-path; "roofline" the dominant kernel (fused stage) against HBM peak;
+path, "mixed_bf16" the path with an FP32 state and BF16 stage increments;
+"roofline" the dominant kernel (fused stage) against HBM peak;
 "cpu_baseline" the FP64 oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
@@ -54,6 +55,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+DTYPE = {0: "f64", 1: "f32-bulk/f64-collision",
+         2: "f32-state/bf16-stage-increments/f64-collision"}
+
+
 def run_gpu(pb, prim_fn, precision, steps, warmup):
     import torch
 
@@ -76,7 +81,11 @@ def run_gpu(pb, prim_fn, precision, steps, warmup):
     dof = s.nx * s.nv
     out = {"dof": dof, "elapsed_s": el, "ms_per_step": 1e3 * el / steps,
            "value": dof * steps / el, "timing": tm, "diag": diag, "dt": dt,
-           "bytes_per_value": 8 if precision == 0 else 4}
+           "precision": precision,
+           # compulsory bytes per DOF per stage launch, averaged over the three
+           # stages: 8s/3 for a stored state of s bytes (read input, [read f^n],
+           # write output); BF16 increments: (4+2, 4+2+2, 4+2+4) B = 8 B
+           "alg_bytes_per_dof": 8.0 if precision == 2 else 8.0 * (8 if precision == 0 else 4) / 3.0}
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -86,18 +95,18 @@ def run_gpu(pb, prim_fn, precision, steps, warmup):
 def roofline(res, steps):
     """Fused stage kernel: algorithmic bytes = compulsory f traffic, 2s (stage 1:
     read input, write output) + 3s + 3s (stages 2, 3: also read f^n) per DOF,
-    i.e. 8s/3 per DOF per launch on average."""
+    i.e. 8s/3 per DOF per launch on average (BF16 increments: 8 B)."""
     tm = res["timing"]
     n = tm["stage_launches"]
     if not n:
         return None
     avg_ms = tm["stage_ms"] / n
-    bytes_per_launch = 8.0 * res["bytes_per_value"] * res["dof"] / 3.0
+    bytes_per_launch = res["alg_bytes_per_dof"] * res["dof"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     try:
         tr = json.load(open(TRAFFIC_FILE))
-        key = f"stage_{'f64' if res['bytes_per_value'] == 8 else 'f32'}"
+        key = "stage_" + {0: "f64", 1: "f32", 2: "bf16"}[res["precision"]]
         if tr.get("source_hash") == kernel_source_hash() and key in tr:
             traffic = tr[key]["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
@@ -187,7 +196,7 @@ def main():
     ap.add_argument("--workload", default="box2d")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="precision of the headline value")
     ap.add_argument("--serving", type=int, default=24, metavar="N",
                     help="requests in the serving mix (0: skip)")
@@ -216,7 +225,7 @@ def main():
                                    "(multi-GPU sharding is a design note only)"}))
         sys.exit(2)
     pb, prim_fn, desc = workload(a.workload)
-    main_prec = 0 if a.precision == "fp64" else 1
+    main_prec = {"fp64": 0, "fp32": 1, "bf16": 2}[a.precision]
     res = run_gpu(pb, prim_fn, main_prec, a.steps, a.warmup)
     print(f"[bench] {a.workload} {a.precision}: {res['value']:.4e} DOF-updates/s, "
           f"{res['ms_per_step']:.3f} ms/step, timing {res['timing']}", file=sys.stderr, flush=True)
@@ -224,7 +233,7 @@ def main():
         "metric": METRIC, "value": res["value"], "unit": "DOF-updates/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if main_prec == 0 else "f32-bulk/f64-collision", "data": "synthetic",
+        "dtype": DTYPE[main_prec], "data": "synthetic",
         "config": {"workload": desc, "dof": res["dof"], "dt": res["dt"],
                    "newton_it_max": res["diag"]["newton_it_max"],
                    "limiter_hits": res["diag"]["limiter_hits"]},
@@ -234,8 +243,13 @@ def main():
         mx = run_gpu(pb, prim_fn, 1, a.steps, a.warmup)
         print(f"[bench] {a.workload} fp32-bulk: {mx['value']:.4e} DOF-updates/s, "
               f"{mx['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-        line["mixed"] = {"dtype": "f32-bulk/f64-collision", "value": mx["value"],
+        line["mixed"] = {"dtype": DTYPE[1], "value": mx["value"],
                          "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps)}
+        bf = run_gpu(pb, prim_fn, 2, a.steps, a.warmup)
+        print(f"[bench] {a.workload} bf16-increments: {bf['value']:.4e} DOF-updates/s, "
+              f"{bf['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        line["mixed_bf16"] = {"dtype": DTYPE[2], "value": bf["value"],
+                              "ms_per_step": bf["ms_per_step"], "roofline": roofline(bf, a.steps)}
     if a.serving:
         sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")),
                      policy=a.serving_policy, max_members=a.serving_members)

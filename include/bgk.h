@@ -83,8 +83,15 @@ typedef enum { BGK_EQ_CONSERVATIVE = 0, BGK_EQ_CONTINUOUS = 1 } bgk_equilibrium;
 
 /* Storage precision of f. FP64: everything in FP64. FP32: f stored and the
  * transport/relaxation/Runge-Kutta arithmetic in FP32; moments, Newton solve
- * and relaxation time in FP64. */
-typedef enum { BGK_FP64 = 0, BGK_FP32 = 1 } bgk_precision;
+ * and relaxation time in FP64. BF16: the state f^n is stored in FP32 and the
+ * two intermediate Runge-Kutta stages as BF16 increments over it (stage s
+ * reads f^n + increment: the explicit stepping of Sec. 2.2, written as
+ * f^(s) = f^n + D_s),
+ * arithmetic as for FP32; per-step rounding is then relative to the
+ * increment, not to f (BF16 values of f itself would swamp the per-step
+ * change). A BF16 solver cannot join a batch (its state buffer alternates
+ * between steps) and has no diffuse walls (BGK_ERR_UNSUPPORTED). */
+typedef enum { BGK_FP64 = 0, BGK_FP32 = 1, BGK_BF16 = 2 } bgk_precision;
 
 typedef enum { BGK_HOST = 0, BGK_DEVICE = 1 } bgk_where;
 

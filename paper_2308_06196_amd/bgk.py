@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bgk.h")
 
 BGK_OK = 0
 BGK_HOST, BGK_DEVICE = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
+PRECISION_NAME = {0: "fp64", 1: "fp32", 2: "bf16"}
 STATUS = {0: "BGK_OK", 1: "BGK_ERR_INVALID_ARG", 2: "BGK_ERR_UNSUPPORTED",
           3: "BGK_ERR_OUT_OF_MEMORY", 4: "BGK_ERR_DEVICE", 5: "BGK_ERR_NEWTON",
           6: "BGK_ERR_NONFINITE", 7: "BGK_ERR_STATE"}

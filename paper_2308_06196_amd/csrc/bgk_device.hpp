@@ -93,7 +93,21 @@ struct StageArgs {
   const double* wallp;
   const double* wall_rho;
   int32_t wall_off[2][2];
+  // BF16-increment stages (FP32 state F, stage increments in BF16): the
+  // stage input is F + din (din null in the first stage), and the output is
+  // the increment o - F in BF16, or o itself in FP32 when out_full is set
+  const uint16_t* din;
+  int32_t out_full;
 };
+
+// BF16 <-> FP32: the upper half of the FP32 bit pattern; rounding to nearest,
+// ties to even (finite inputs).
+__device__ __forceinline__ float bf16_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f32_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
 
 // Diffuse walls: outgoing mass flux per wall flux point and velocity chunk
 // (k_wall_flux), then the re-emitted density per flux point (k_wall_rho).
@@ -419,10 +433,11 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
 // a = 0, which does not read f^n), or the plain residual L(f) in FP64
 // (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
 // ---------------------------------------------------------------------------
-template <int DIM, int P, typename ST, int MODE>
+template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 3 : 4)))
     k_stage(const StageArgs A) {
+  static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
@@ -519,14 +534,31 @@ __global__ void __launch_bounds__(kBlock)
       tv[u] = et[t < ntab ? t : ntab - 1];
     }
   }
+  // BF16-increment stages 2-3: the input is F + increment (same offsets)
+  constexpr bool kDin = INC && MODE == 0;
+  const uint16_t* __restrict__ din = A.din;
   const ST* fe = fin + f_offset(g, e, 0, jj);
   CT f[NS];
+  CT fb[kDin ? NS : 1];  // F of the own nodes (the f^n of the combine)
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[i * kVB];
+  if constexpr (kDin) {
+    const uint16_t* de = din + (fe - fin);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      fb[i] = f[i];
+      f[i] += bf16_f32(de[i * kVB]);
+    }
+  }
   CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
   if constexpr (kPreload) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) nbv[0][i] = (CT)src[0][i * kVB];
+    if constexpr (kDin) {
+      const uint16_t* ds = din + (src[0] - fin);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) nbv[0][i] += bf16_f32(ds[i * kVB]);
+    }
   }
   // equilibrium rows (NS x S) of this element -> LDS
   if (A.collide) {
@@ -551,6 +583,11 @@ __global__ void __launch_bounds__(kBlock)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][i * kVB];
+        if constexpr (kDin) {
+          const uint16_t* ds = din + (src[k] - fin);
+#pragma unroll
+          for (int i = 0; i < NS; ++i) nbv[k][i] += bf16_f32(ds[i * kVB]);
+        }
       }
     }
     const CT a = (CT)(vel.u[k] * g.scale[k]);
@@ -599,8 +636,10 @@ __global__ void __launch_bounds__(kBlock)
         CT xv;
         if constexpr (kPreload)
           xv = nbv[k][base + bb * S1];
-        else
+        else {
           xv = (CT)src[k][(base + bb * S1) * kVB];
+          if constexpr (kDin) xv += bf16_f32(din[(src[k] - fin) + (base + bb * S1) * kVB]);
+        }
         ext += lext[bb] * xv;
       }
       if (dwall) {  // uniform: the element touches a diffuse wall of axis k
@@ -622,7 +661,10 @@ __global__ void __launch_bounds__(kBlock)
 
   // f^n: needed only by the final combine, in flight during the relaxation
   CT fnv[NS];
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 && INC) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) fnv[i] = fb[i];
+  } else if constexpr (MODE == 0) {
     const ST* fn = (const ST*)A.fn + f_offset(g, e, 0, jj);
 #pragma unroll
     for (int i = 0; i < NS; ++i) fnv[i] = (CT)fn[i * kVB];
@@ -684,11 +726,32 @@ __global__ void __launch_bounds__(kBlock)
         if (nb) atomicAdd(&A.diag[3], nb);
       }
     }
-    ST* out = (ST*)A.out;
-    if (valid) {
-      ST* oe = out + f_offset(g, e, 0, j);
+    if constexpr (INC) {
+      // the increment o - F in BF16, and the stored state F + increment for
+      // the partials; the last stage stores o itself in FP32
+      if (A.out_full) {
+        if (valid) {
+          ST* oe = (ST*)A.out + f_offset(g, e, 0, j);
 #pragma unroll
-      for (int i = 0; i < NS; ++i) oe[i * kVB] = (ST)o[i];
+          for (int i = 0; i < NS; ++i) oe[i * kVB] = (ST)o[i];
+        }
+      } else {
+        uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, 0, jj);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const CT base = MODE == 0 ? fnv[i] : f[i];
+          const uint16_t h = f32_bf16(o[i] - base);
+          if (valid) oe[i * kVB] = h;
+          o[i] = base + bf16_f32(h);
+        }
+      }
+    } else {
+      ST* out = (ST*)A.out;
+      if (valid) {
+        ST* oe = out + f_offset(g, e, 0, j);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) oe[i * kVB] = (ST)o[i];
+      }
     }
     // moment partials of what was stored (FP64 sums on the matrix cores); the
     // staging area reuses the equilibrium rows' LDS once every wave is done

@@ -97,10 +97,11 @@ __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2
 }
 
 
-template <int P, typename ST, int MODE>
+template <int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 2 : 3)))
     k_stage3(const StageArgs A) {
+  static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
   constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
@@ -181,6 +182,9 @@ __global__ void __launch_bounds__(kBlock)
       tv[u] = et[t < ntab ? t : ntab - 1];
     }
   }
+  // BF16-increment stages 2-3: the input is F + increment (same offsets)
+  constexpr bool kDin = INC && MODE == 0;
+  const uint16_t* __restrict__ din = A.din;
   const ST* fe = fin + f_offset(g, e, pl * P2, jj);
   CT f[P2];
 #pragma unroll
@@ -190,8 +194,21 @@ __global__ void __launch_bounds__(kBlock)
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][q * kVB];
-  CT fnv[P2];  // last: needed only by the final combine
-  if constexpr (MODE == 0) {
+  CT fnv[P2];  // needed only by the final combine (F of the own nodes for increments)
+  if constexpr (kDin) {
+    const uint16_t* de = din + (fe - fin);
+#pragma unroll
+    for (int q = 0; q < P2; ++q) {
+      fnv[q] = f[q];
+      f[q] += bf16_f32(de[q * kVB]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint16_t* ds = din + (src[k] - fin);
+#pragma unroll
+      for (int q = 0; q < P2; ++q) nb[k][q] += bf16_f32(ds[q * kVB]);
+    }
+  } else if constexpr (MODE == 0) {
     const ST* fn = (const ST*)A.fn + f_offset(g, e, pl * P2, jj);
 #pragma unroll
     for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[q * kVB];
@@ -341,7 +358,26 @@ __global__ void __launch_bounds__(kBlock)
         if (nb2) atomicAdd(&A.diag[3], nb2);
       }
     }
-    if (act) {
+    if constexpr (INC) {
+      // the increment o - F in BF16, and the stored state F + increment for
+      // the partials; the last stage stores o itself in FP32
+      if (A.out_full) {
+        if (act) {
+          ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);
+#pragma unroll
+          for (int q = 0; q < P2; ++q) oe[q * kVB] = (ST)o[q];
+        }
+      } else {
+        uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, pl * P2, jj);
+#pragma unroll
+        for (int q = 0; q < P2; ++q) {
+          const CT base = MODE == 0 ? fnv[q] : f[q];
+          const uint16_t h = f32_bf16(o[q] - base);
+          if (act) oe[q * kVB] = h;
+          o[q] = base + bf16_f32(h);
+        }
+      }
+    } else if (act) {
       ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);
 #pragma unroll
       for (int q = 0; q < P2; ++q) oe[q * kVB] = (ST)o[q];

@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256) k_to_canonical(const DevGeom g, const SRC
 static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <typename ST>
-static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
+static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStream_t s) {
   const dim3 grid((unsigned)(A.g.nchunk * A.ecount)), block(kBlock);
   const int key = A.g.dim * 10 + (A.g.n1 - 1);
   // dynamic LDS: equilibrium rows (relaxation), then, in the 1-D/2-D
@@ -435,6 +435,15 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   const size_t lds = mode != 1 ? std::max(tab, (size_t)mfma_lds_bytes<ST>()) : tab;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
+    if constexpr (sizeof(ST) == 4) {                                       \
+      if (mode == 0 && inc) {                                              \
+        if (A.din)                                                         \
+          hipLaunchKernelGGL((k_stage<D, P, ST, 0, true>), grid, block, lds, s, A); \
+        else                                                               \
+          hipLaunchKernelGGL((k_stage<D, P, ST, 3, true>), grid, block, lds, s, A); \
+        break;                                                             \
+      }                                                                    \
+    }                                                                      \
     if (mode == 0 && A.a != 0.0)                                           \
       hipLaunchKernelGGL((k_stage<D, P, ST, 0>), grid, block, lds, s, A);  \
     else if (mode == 0)                                                    \
@@ -448,6 +457,15 @@ static hipError_t stage_dispatch(int mode, const StageArgs& A, hipStream_t s) {
   case 30 + P: {                                                           \
     const size_t lds3 =                                                    \
         mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
+    if constexpr (sizeof(ST) == 4) {                                       \
+      if (mode == 0 && inc) {                                              \
+        if (A.din)                                                         \
+          hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3, s, A); \
+        else                                                               \
+          hipLaunchKernelGGL((k_stage3<P, ST, 3, true>), grid, block, lds3, s, A); \
+        break;                                                             \
+      }                                                                    \
+    }                                                                      \
     if (mode == 0 && A.a != 0.0)                                           \
       hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds3, s, A);   \
     else if (mode == 0)                                                    \
@@ -477,7 +495,10 @@ int velocities_per_block(int dim, int order) {
 
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s) {
   if (A.ecount <= 0) return hipSuccess;
-  return precision == 0 ? stage_dispatch<double>(mode, A, s) : stage_dispatch<float>(mode, A, s);
+  // BF16 storage (precision 2): FP32 state with BF16 stage increments; the
+  // RK stages use the increment kernels, everything else the FP32 ones
+  return precision == 0 ? stage_dispatch<double>(mode, false, A, s)
+                        : stage_dispatch<float>(mode, precision == 2, A, s);
 }
 
 template <typename ST>

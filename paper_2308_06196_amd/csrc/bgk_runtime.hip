@@ -163,7 +163,8 @@ struct Layout {
   int64_t nx, nv, ne, nvb;
   int ns, nchunk;
   int64_t wall_points;  // flux points on diffuse walls
-  size_t fbytes;
+  size_t fbytes;   // one FP64/FP32 state buffer
+  size_t fsz[3];   // bytes of f(0), f(1), f(2)
 };
 
 // Flux points of the diffuse walls: side (k, s) holds ne / nelem[k] faces of
@@ -183,8 +184,8 @@ bgk_status validate(const bgk_problem* pb) {
   if (pb->dim < 1 || pb->dim > 3) return fail(BGK_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
   if (pb->order < 1 || pb->order > 3)
     return fail(BGK_ERR_UNSUPPORTED, "order %d not built (1..3)", pb->order);
-  if (pb->precision != BGK_FP64 && pb->precision != BGK_FP32)
-    return fail(BGK_ERR_INVALID_ARG, "precision must be BGK_FP64 or BGK_FP32");
+  if (pb->precision != BGK_FP64 && pb->precision != BGK_FP32 && pb->precision != BGK_BF16)
+    return fail(BGK_ERR_INVALID_ARG, "precision must be BGK_FP64, BGK_FP32 or BGK_BF16");
   if (pb->limiter != 0 && pb->limiter != 1)
     return fail(BGK_ERR_INVALID_ARG, "limiter must be 0 or 1");
   if (pb->equilibrium != BGK_EQ_CONSERVATIVE && pb->equilibrium != BGK_EQ_CONTINUOUS)
@@ -199,6 +200,8 @@ bgk_status validate(const bgk_problem* pb) {
       if (pb->bc[k][s] == BGK_BC_DIFFUSE) {
         if (pb->dim == 3)
           return fail(BGK_ERR_UNSUPPORTED, "diffuse walls are built for 1-D and 2-D meshes");
+        if (pb->precision == BGK_BF16)
+          return fail(BGK_ERR_UNSUPPORTED, "diffuse walls are built for FP64 and FP32 storage");
         if (!(pb->wall_theta[k][s] > 0.0))
           return fail(BGK_ERR_INVALID_ARG, "wall_theta[%d][%d] must be > 0", k, s);
       }
@@ -242,10 +245,15 @@ Layout layout_of(const bgk_problem* pb) {
   const size_t s = pb->precision == BGK_FP64 ? 8 : 4;
   L.nvb = (L.nv + kVB - 1) / kVB;
   L.fbytes = (size_t)L.nx * (size_t)(L.nvb * kVB) * s;  // internal layout, padded blocks
+  // FP64/FP32: three state-precision buffers (f^n, f^(1), f^(2)). BF16: two
+  // FP32 buffers that alternate as f^n and f^(n+1) (the first increment lives
+  // in the second one) and one BF16 buffer for the second increment.
+  L.fsz[0] = L.fsz[1] = L.fbytes;
+  L.fsz[2] = pb->precision == BGK_BF16 ? L.fbytes / 2 : L.fbytes;
   size_t off = 0;
   for (int b = 0; b < 3; ++b) {
     L.f[b] = off;
-    off = align_up(off + L.fbytes);
+    off = align_up(off + L.fsz[b]);
   }
   L.partials = off;
   off = align_up(off + (size_t)L.nx * L.nchunk * 5 * sizeof(double));
@@ -295,7 +303,9 @@ struct bgk_solver {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<int> kinds;
+  int cur = 0;  // state buffer (BF16 storage alternates between f(0) and f(1))
   void* f(int b) const { return ws + L.f[b]; }
+  void* state() const { return f(cur); }
   double* partials() const { return (double*)(ws + L.partials); }
   double* params() const { return (double*)(ws + L.params); }
   double* etab() const { return (double*)(ws + L.etab); }
@@ -371,7 +381,7 @@ NewtonArgs newton_args(const bgk_solver* s) {
   N.tol = s->pb.newton_tol > 0.0 ? s->pb.newton_tol : 1e-14;
   N.maxit = s->pb.newton_maxit > 0 ? s->pb.newton_maxit : 20;
   N.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
-  N.etab_f32 = s->precision == BGK_FP32 ? 1 : 0;
+  N.etab_f32 = s->precision != BGK_FP64 ? 1 : 0;
   N.continuous = s->pb.equilibrium == BGK_EQ_CONTINUOUS ? 1 : 0;
   return N;
 }
@@ -502,7 +512,7 @@ bgk_status moments_of(bgk_solver* s, const void* fstore) {
 
 bgk_status ensure_partials(bgk_solver* s) {
   if (!s->partials_valid) {
-    bgk_status st = moments_of(s, s->f(0));
+    bgk_status st = moments_of(s, s->state());
     if (st) return st;
     s->partials_valid = true;
   }
@@ -724,9 +734,11 @@ bgk_status bgk_set_state(bgk_solver* s, const double* f, int32_t where) {
   if (where == BGK_DEVICE) {
     HIP_TRY(launch_to_storage(s->precision, s->g, f, s->f(0), 0, n, s->stream));
   } else {
-    bgk_status st = host_to_storage(s, f, s->f(0), n, (char*)s->f(1), 2 * s->L.fbytes);
+    bgk_status st = host_to_storage(s, f, s->f(0), n, (char*)s->f(1),
+                                    s->L.f[2] + s->L.fsz[2] - s->L.f[1]);
     if (st) return st;
   }
+  s->cur = 0;
   return reset_state_flags(s);
 }
 
@@ -743,6 +755,7 @@ bgk_status bgk_set_maxwellian(bgk_solver* s, const double* prim, int32_t where) 
     dprim = s->prim();
   }
   HIP_TRY(launch_maxwellian(s->precision, s->g, dprim, s->f(0), s->stream));
+  s->cur = 0;
   bgk_status st = reset_state_flags(s);
   if (where == BGK_HOST) HIP_TRY(hipStreamSynchronize(s->stream));
   return st;
@@ -754,9 +767,12 @@ bgk_status bgk_get_state(bgk_solver* s, double* f, int32_t where) {
   if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
   const int64_t n = s->L.nx * s->L.nv;
   if (where == BGK_DEVICE) {
-    HIP_TRY(launch_from_storage(s->precision, s->g, s->f(0), f, 0, n, s->stream));
+    HIP_TRY(launch_from_storage(s->precision, s->g, s->state(), f, 0, n, s->stream));
   } else {
-    bgk_status st = storage_to_host(s, s->f(0), f, n, (char*)s->f(1), 2 * s->L.fbytes);
+    // staging: device memory that does not hold the state
+    char* stage = (char*)(s->cur == 0 ? s->f(1) : s->f(0));
+    const size_t cap = s->cur == 0 ? s->L.f[2] + s->L.fsz[2] - s->L.f[1] : s->L.fsz[0];
+    bgk_status st = storage_to_host(s, s->state(), f, n, stage, cap);
     if (st) return st;
   }
   return check_failed(s);
@@ -772,16 +788,18 @@ bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_
     if (st) return st;
   }
   const int64_t n = s->L.nx * s->L.nv;
-  const void* fin = s->f(0);
+  const void* fin = s->state();
   if (f_in) {
+    // f_in goes to the state-precision buffer that does not hold the state
+    void* dst = s->f(1 - s->cur);
     if (where == BGK_DEVICE) {
-      HIP_TRY(launch_to_storage(s->precision, s->g, f_in, s->f(1), 0, n, s->stream));
+      HIP_TRY(launch_to_storage(s->precision, s->g, f_in, dst, 0, n, s->stream));
     } else {
       // staged through f2
-      bgk_status st = host_to_storage(s, f_in, s->f(1), n, (char*)s->f(2), s->L.fbytes);
+      bgk_status st = host_to_storage(s, f_in, dst, n, (char*)s->f(2), s->L.fsz[2]);
       if (st) return st;
     }
-    fin = s->f(1);
+    fin = dst;
     bgk_status st = moments_of(s, fin);
     if (st) return st;
     s->partials_valid = false;  // the partials now belong to f_in
@@ -804,7 +822,7 @@ bgk_status bgk_residual(bgk_solver* s, const double* f_in, double* r_out, int32_
   }
   // host output: element ranges that fit the f2 region as FP64
   const size_t per_elem = (size_t)s->L.ns * s->L.nv * 8;
-  const int64_t cap = (int64_t)(s->L.fbytes / per_elem);
+  const int64_t cap = (int64_t)(s->L.fsz[2] / per_elem);
   if (cap < 1)
     return fail(BGK_ERR_UNSUPPORTED, "host residual with FP32 storage needs >= 2 elements; "
                 "use device buffers");
@@ -835,21 +853,34 @@ bgk_status rk3_launch(bgk_solver* s, double dt, int32_t nsteps, hipStream_t st, 
   N.Q = nullptr;
   StageArgs A = stage_args(s);
   A.dt = dt;
-  A.fn = s->f(0);
+  const bool inc = s->precision == BGK_BF16;
   if (timed) {
     if (s->used > 0) s->kinds.push_back(2);  // host gap between calls: not a kernel
     if ((rc = mark(s))) return rc;
   }
   for (int32_t step = 0; step < nsteps; ++step) {
+    // FP64/FP32: f(0) = f^n -> f(1) -> f(2) -> f(0) (the last stage reads f^n
+    // only at its own point, so it may overwrite it). BF16: F = f(cur) is
+    // f^n; the first increment goes to f(1 - cur) (as BF16), the second to
+    // f(2), and f^(n+1) to f(1 - cur) in FP32, which then holds the state.
+    const int fa = s->cur, fb = 1 - s->cur;
+    A.fn = s->f(fa);
     for (int k = 0; k < 3; ++k) {
       HIP_TRY(launch_newton(N, st));
-      if ((rc = wall_densities(s, s->f(k), st))) return rc;
+      if (!inc && (rc = wall_densities(s, s->f(k), st))) return rc;
       if (timed) {
         s->kinds.push_back(0);
         if ((rc = mark(s))) return rc;
       }
-      A.fin = s->f(k);
-      A.out = s->f((k + 1) % 3);
+      if (inc) {
+        A.fin = s->f(fa);
+        A.din = k == 0 ? nullptr : (const uint16_t*)(k == 1 ? s->f(fb) : s->f(2));
+        A.out = k == 1 ? s->f(2) : s->f(fb);
+        A.out_full = k == 2;
+      } else {
+        A.fin = s->f(k);
+        A.out = s->f((k + 1) % 3);
+      }
       A.a = kA[k];
       A.b = kB[k];
       HIP_TRY(launch_stage(s->precision, 0, A, st));
@@ -858,6 +889,7 @@ bgk_status rk3_launch(bgk_solver* s, double dt, int32_t nsteps, hipStream_t st, 
         if ((rc = mark(s))) return rc;
       }
     }
+    if (inc) s->cur = fb;
   }
   return BGK_OK;
 }
@@ -1125,6 +1157,9 @@ bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps)
   if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
   if (s->failed) return fail(BGK_ERR_STATE, "solver failed earlier; install a new state");
   if (s->timing) return fail(BGK_ERR_STATE, "disable timing before adding to a batch");
+  if (s->precision == BGK_BF16)
+    return fail(BGK_ERR_UNSUPPORTED, "BF16 storage alternates its state buffer between steps; "
+                "step it with bgk_rk3_step");
   bgk_status st = ensure_partials(s);
   if (st) return st;
   s->in_batch = true;

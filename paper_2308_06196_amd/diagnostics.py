@@ -10,8 +10,9 @@ taken from the macroscopic moments the library computes on the GPU
 
 where curl U uses the element-local derivative of the nodal velocity
 (Lagrange interpolation on the Gauss points). A history runs the workload in
-FP64 and in FP32 storage side by side; no reference data exists for this
-configuration, so the FP32 history is compared against the FP64 one.
+FP64, FP32 and BF16-increment storage side by side; no reference data exists
+for this configuration, so the FP32 and BF16 histories are compared against
+the FP64 one.
 
 Usage: python -m paper_2308_06196_amd.diagnostics [--n 16] [--steps 100] [--every 10]
 """
@@ -68,7 +69,7 @@ def integrals(pb: dict, Q: np.ndarray, gamma: float = 5.0 / 3.0) -> dict:
 
 
 def tgv_history(n: int = 16, order: int = 3, nv1: int = 16, steps: int = 100, every: int = 10,
-                precisions=(bgk.FP64, bgk.FP32), cfl: float = 0.1) -> list:
+                precisions=(bgk.FP64, bgk.FP32, bgk.BF16), cfl: float = 0.1) -> list:
     """Kinetic energy and enstrophy every `every` steps of the Taylor-Green box in
     each storage precision (same time step for all)."""
     pb = wl.tgv3d(n=n, order=order, nv1=nv1)
@@ -84,8 +85,7 @@ def tgv_history(n: int = 16, order: int = 3, nv1: int = 16, steps: int = 100, ev
                 if k:
                     s.rk3_step(dt, every)
                 r = integrals(pb, s.moments().cpu().numpy())
-                r.update({"precision": "fp64" if prec == bgk.FP64 else "fp32", "step": k,
-                          "t": k * dt})
+                r.update({"precision": bgk.PRECISION_NAME[prec], "step": k, "t": k * dt})
                 rows.append(r)
         finally:
             s.close()
@@ -104,13 +104,14 @@ def main(argv=None):
     for r in rows:
         print(json.dumps(r), flush=True)
     f64 = {r["step"]: r for r in rows if r["precision"] == "fp64"}
-    print("| step | t | K (FP64) | Z (FP64) | rel. diff K (FP32) | rel. diff Z (FP32) |")
-    print("|---|---|---|---|---|---|")
+    print("| step | t | K (FP64) | Z (FP64) | storage | rel. diff K | rel. diff Z |")
+    print("|---|---|---|---|---|---|---|")
     for r in rows:
-        if r["precision"] != "fp32":
+        if r["precision"] == "fp64":
             continue
         b = f64[r["step"]]
         print(f"| {r['step']} | {r['t']:.4f} | {b['kinetic_energy']:.6e} | {b['enstrophy']:.6e} | "
+              f"{r['precision']} | "
               f"{abs(r['kinetic_energy'] - b['kinetic_energy']) / b['kinetic_energy']:.1e} | "
               f"{abs(r['enstrophy'] - b['enstrophy']) / b['enstrophy']:.1e} |")
 

@@ -53,8 +53,24 @@ def test_footprint_scales_with_precision():
     pb = wl.box2d()
     b64, nx, nv = bgk.footprint(pb, bgk.FP64)
     b32, _, _ = bgk.footprint(pb, bgk.FP32)
+    b16, _, _ = bgk.footprint(pb, bgk.BF16)
     assert nx == 1024 * 16 and nv == 24 ** 3
     assert b64 >= 3 * nx * nv * 8 and b32 >= 3 * nx * nv * 4 and b32 < b64
+    # BF16: two FP32 state buffers and one BF16 increment buffer
+    assert b16 >= nx * nv * 10 and b16 < b32
+
+
+def test_bf16_precision_limits():
+    """BF16 storage (FP32 state, BF16 stage increments) is accepted; an unknown
+    precision is an argument error and diffuse walls are not built for it."""
+    bgk.footprint(wl.box2d(n=2), bgk.BF16)
+    with pytest.raises(bgk.BGKError) as ei:
+        bgk.footprint(wl.box2d(n=2), 3)
+    assert ei.value.status == 1
+    with pytest.raises(bgk.BGKError) as ei:
+        bgk.footprint(wl.channel2d(nx=2, ny=2), bgk.BF16)
+    assert ei.value.status == 2
+    bgk.footprint(wl.channel2d(nx=2, ny=2), bgk.FP32)
 
 
 def _host_only_solver(pb, precision=bgk.FP64):

@@ -401,3 +401,82 @@ def test_viscosity_laws_match_oracle(torch, name, law):
     s.rk3_step(dt, 3)
     f_orc, _ = orc.rk3_step(pr, f0, dt, 3)
     assert rel_max(s.get_state().cpu().numpy(), f_orc) < 1e-12
+
+
+def _bf16_bound(pr, f0, dt, n):
+    """Oracle trajectory of n steps and the error bound of the BF16-increment path.
+
+    A BF16 value is rounded to nearest with relative error <= 2^-8. The stored
+    increments of a step are D1 = dt L(f^n) and D2 ~ (D1 + dt L(f1)) / 4, and
+    the rounding of D1 reaches D2 and f^(n+1) through stable stages, so each
+    step carries at most ~(4/3) 2^-8 max|dt L(f^n)| into the state. The bound
+    doubles that per step and adds the FP32 arithmetic (1e-5 max|f|)."""
+    traj, inc = [f0], 0.0
+    for _ in range(n):
+        L, _ = orc.residual(pr, traj[-1])
+        inc = max(inc, dt * float(np.abs(L).max()))
+        traj.append(orc.rk3_step(pr, traj[-1], dt, 1)[0])
+    return traj, 1e-5 * float(np.abs(traj[-1]).max()) + 2.0 * n * 2.0 ** -8 * inc
+
+
+@pytest.mark.parametrize("name", ["d1p2_sod_spec", "d2p2_box", "d2p3_box", "d3p1_tgv",
+                                  "d3p2_tgv", "d3p3_tgv"])
+def test_bf16_increments_rk3_matches_oracle(torch, name):
+    """BF16 storage (FP32 f^n, BF16 stage increments): 3 steps against the FP64
+    oracle within the bound of _bf16_bound; the same steps in FP32 storage stay
+    within 1e-5, so the difference is the increment rounding."""
+    pb, kind = CASES[name]
+    _say("rk3-bf16", name)
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, kind, seed=8, amp=0.2)
+    dt = orc.stable_dt(pr, f0, 0.1)
+    traj, bound = _bf16_bound(pr, f0, dt, 3)
+    s = solver(pb, precision=2)
+    s.set_state(dev(torch, f0))
+    s.rk3_step(dt, 3)
+    err = float(np.abs(s.get_state().cpu().numpy() - traj[-1]).max())
+    print(f"bf16 {name}: err {err:.3e} bound {bound:.3e} (max f {np.abs(traj[-1]).max():.3e})")
+    assert err < bound
+    s.diagnostics()
+
+
+def test_bf16_fields_and_state_buffers(torch):
+    """BF16 increments over 20 steps of the 2-D box: per-field errors against the
+    oracle, the state exchange after an odd and an even number of steps (the
+    state alternates between two FP32 buffers), the residual entry point, and
+    batches refusing a BF16 solver."""
+    from paper_2308_06196_amd import bgk
+    pb = wl.box2d(n=4)
+    _say("box2d-bf16", pb["nelem"])
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "box2d")
+    dt = orc.stable_dt(pr, f0, 0.1)
+    traj, bound = _bf16_bound(pr, f0, dt, 20)
+    s = solver(pb, precision=2)
+    s.set_state(dev(torch, f0))
+    s.rk3_step(dt, 19)
+    assert rel_max(s.get_state().cpu().numpy(), traj[19], scale=1.0) < bound
+    s.rk3_step(dt, 1)
+    f20 = s.get_state().cpu().numpy()
+    assert rel_max(f20, traj[20], scale=1.0) < bound
+    errs = field_errors(pb, s.moments().cpu().numpy(), orc.moments(pr, traj[20]))
+    print("bf16 field errors", errs, "state bound", bound)
+    assert max(errs.values()) < 1e-4, errs
+    # the residual of the installed state runs the FP32 kernel on the FP32
+    # state: the same result as an FP32 solver holding the same values
+    L = s.residual().cpu().numpy()
+    s32 = solver(pb, precision=1)
+    s32.set_state(dev(torch, f20))
+    L32 = s32.residual().cpu().numpy()
+    assert np.abs(L - L32).max() <= 1e-12 * np.abs(L32).max()
+    s32.close()
+    s.synchronize()
+    st = torch.cuda.Stream()
+    sb = bgk.Solver(pb, precision=2, stream=st)
+    sb.set_state(dev(torch, f0))
+    b = bgk.Batch(st, max_members=2)
+    with pytest.raises(bgk.BGKError) as ei:
+        b.add(sb, dt, 1)
+    assert ei.value.status == 2
+    b.close()
+    sb.close()
