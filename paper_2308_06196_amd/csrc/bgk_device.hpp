@@ -326,7 +326,8 @@ __device__ __forceinline__ void table_rest(CT* tab, const ST* et, int ntab) {
 // velocity's node values, and w psi of its velocity) to LDS; wave_moments_4x4
 // reads the operands back and runs the products. The four waves' tiles are
 // then added in a fixed order. `stage` is the work-group's MFMA staging area
-// (mfma_lds_bytes<ST>() bytes), `red` 4 x 16 x 5 doubles.
+// (mfma_lds_bytes<ST>() bytes: 16 rows per wave, one tile of 16 nodes at a
+// time), `red` 4 x part_rows<NS>() x 5 doubles.
 constexpr int kGst = 66;  // LDS row stride (elements) of the staged node values
 template <typename ST>
 constexpr int mfma_lds_bytes() {
@@ -393,35 +394,57 @@ __device__ __forceinline__ void wave_moments_4x4(const ST* gw, int rs, const dou
   }
 }
 
+// Rows of the per-wave partial sums of an element of NS nodes (tiles of 16).
+template <int NS>
+constexpr int part_rows() {
+  return (NS + 15) / 16 * 16;
+}
+
+// Tile T of 16 nodes: stage the values, then the products (the staging rows
+// are reused by the next tile once this wave has read them).
+template <int T, int NS, typename ST, typename CT>
+__device__ __forceinline__ void element_tiles(const CT (&fv)[NS], ST* gw, const double* ps,
+                                              double* redw) {
+  if constexpr (16 * T < NS) {
+    constexpr int NV = NS - 16 * T < 16 ? NS - 16 * T : 16;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) gw[i * kGst + lane] = (ST)fv[16 * T + i];
+    // the lanes of this wave read what the others wrote (LDS is ordered
+    // within a wave; the fences keep the compiler from moving accesses across)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    wave_moments_4x4<1, NV, 64, ST>(gw, kGst, ps, redw + 16 * T * 5);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    element_tiles<T + 1, NS, ST, CT>(fv, gw, ps, redw);
+  }
+}
+
 template <int NS, typename ST, typename CT>
 __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const Vel& vel,
                                                       double* __restrict__ partials,
                                                       int64_t node0, int64_t nx, int chunk,
                                                       unsigned char* stage, double* red) {
-  static_assert(NS <= 16, "the nodes of an element fill at most one 16-row tile");
+  constexpr int NR = part_rows<NS>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* ps = reinterpret_cast<double*>(stage) + wave * 64 * 5;
   ST* gw = reinterpret_cast<ST*>(stage + (kBlock / 64) * 64 * 5 * sizeof(double)) + wave * 16 * kGst;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) gw[i * kGst + lane] = (ST)fv[i];
   const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
   ps[lane * 5 + 0] = vel.w;
   ps[lane * 5 + 1] = vel.w * vel.u[0];
   ps[lane * 5 + 2] = vel.w * vel.u[1];
   ps[lane * 5 + 3] = vel.w * vel.u[2];
   ps[lane * 5 + 4] = vel.w * psi4;
-  // the lanes of this wave read what the others wrote (LDS is ordered within
-  // a wave; the fences keep the compiler from moving the reads up)
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  wave_moments_4x4<1, NS, 64, ST>(gw, kGst, ps, red + wave * 16 * 5);
+  element_tiles<0, NS, ST, CT>(fv, gw, ps, red + wave * NR * 5);
   lds_barrier();
   for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
     const int node = t / 5, m = t - node * 5;
     double sum = red[node * 5 + m];
 #pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) sum += red[(w * 16 + node) * 5 + m];
+    for (int w = 1; w < kBlock / 64; ++w) sum += red[(w * NR + node) * 5 + m];
     partials[((int64_t)chunk * nx + node0 + node) * 5 + m] = sum;
   }
 }
@@ -433,9 +456,19 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
 // a = 0, which does not read f^n), or the plain residual L(f) in FP64
 // (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
 // ---------------------------------------------------------------------------
+// Waves per SIMD the stage kernel is built for: FP32 quadrilaterals 4, FP64
+// quadrilaterals 3; hexahedra (one lane per velocity with all (p+1)^3 nodes,
+// FP32 storage) 3 at p = 2 and 2 at p = 3 (measured: a few spilled registers
+// at p = 3 cost less than halving the waves; at p = 2 four waves' spills cost
+// a third of the time).
+template <int DIM, int P, typename CT>
+constexpr int stage_waves() {
+  return DIM == 3 && P == 3 ? 2 : DIM == 3 && P == 2 ? 3 : sizeof(CT) == 8 ? 3 : 4;
+}
+
 template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 3 : 4)))
+    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T>())))
     k_stage(const StageArgs A) {
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
@@ -445,7 +478,7 @@ __global__ void __launch_bounds__(kBlock)
   // when they fit the register budget (1-D and 2-D elements); otherwise each
   // value is read where it is used
   constexpr bool kPreload = NS * DIM <= 48;
-  __shared__ double red[(kBlock / 64) * 16 * 5];
+  __shared__ double red[(kBlock / 64) * part_rows<NS>() * 5];
   __shared__ FaceRows<CT> frows[kBlock / 64];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   CT* tab = reinterpret_cast<CT*>(dyn_lds);
@@ -534,19 +567,22 @@ __global__ void __launch_bounds__(kBlock)
       tv[u] = et[t < ntab ? t : ntab - 1];
     }
   }
-  // BF16-increment stages 2-3: the input is F + increment (same offsets)
+  // BF16-increment stages 2-3: the input is F + increment (same offsets).
+  // F of the own nodes (the f^n of the combine) stays in registers for small
+  // elements and is read again (a cache hit) for hexahedra.
   constexpr bool kDin = INC && MODE == 0;
+  constexpr bool kKeepF = kDin && NS <= 16;
   const uint16_t* __restrict__ din = A.din;
   const ST* fe = fin + f_offset(g, e, 0, jj);
   CT f[NS];
-  CT fb[kDin ? NS : 1];  // F of the own nodes (the f^n of the combine)
+  CT fb[kKeepF ? NS : 1];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[i * kVB];
   if constexpr (kDin) {
     const uint16_t* de = din + (fe - fin);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      fb[i] = f[i];
+      if constexpr (kKeepF) fb[i] = f[i];
       f[i] += bf16_f32(de[i * kVB]);
     }
   }
@@ -661,9 +697,12 @@ __global__ void __launch_bounds__(kBlock)
 
   // f^n: needed only by the final combine, in flight during the relaxation
   CT fnv[NS];
-  if constexpr (MODE == 0 && INC) {
+  if constexpr (kKeepF) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) fnv[i] = fb[i];
+  } else if constexpr (kDin) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fe[i * kVB];
   } else if constexpr (MODE == 0) {
     const ST* fn = (const ST*)A.fn + f_offset(g, e, 0, jj);
 #pragma unroll
@@ -768,7 +807,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   using CT = typename Compute<ST>::T;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
-  __shared__ double red[(kBlock / 64) * 16 * 5];
+  __shared__ double red[(kBlock / 64) * part_rows<NS>() * 5];
   extern __shared__ __align__(16) unsigned char dyn_lds[];  // MFMA staging
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);

@@ -453,19 +453,39 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
     else                                                                   \
       hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, lds, s, A);   \
     break;
+// Hexahedra: FP32 storage runs the one-lane-per-velocity kernels (all
+// (p+1)^3 nodes of the element in one lane's registers); FP64 storage, and
+// BF16 increments (which add a second value per neighbour node), the
+// plane-split kernels, whose lanes hold one z-plane each. The choice is per
+// solver, so that all its kernels share one velocity-chunk width.
 #define BGK_CASE3(P)                                                       \
   case 30 + P: {                                                           \
-    const size_t lds3 =                                                    \
-        mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
     if constexpr (sizeof(ST) == 4) {                                       \
-      if (mode == 0 && inc) {                                              \
-        if (A.din)                                                         \
-          hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3, s, A); \
+      if (inc) {                                                           \
+        const size_t lds3i =                                               \
+            mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
+        if (mode == 0 && A.din)                                            \
+          hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3i, s, A); \
+        else if (mode == 0)                                                \
+          hipLaunchKernelGGL((k_stage3<P, ST, 3, true>), grid, block, lds3i, s, A); \
+        else if (mode == 1)                                                \
+          hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds3i, s, A); \
         else                                                               \
-          hipLaunchKernelGGL((k_stage3<P, ST, 3, true>), grid, block, lds3, s, A); \
+          hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, lds3i, s, A); \
         break;                                                             \
       }                                                                    \
+      if (mode == 0 && A.a != 0.0)                                         \
+        hipLaunchKernelGGL((k_stage<3, P, ST, 0>), grid, block, lds, s, A); \
+      else if (mode == 0)                                                  \
+        hipLaunchKernelGGL((k_stage<3, P, ST, 3>), grid, block, lds, s, A); \
+      else if (mode == 1)                                                  \
+        hipLaunchKernelGGL((k_stage<3, P, ST, 1>), grid, block, lds, s, A); \
+      else                                                                 \
+        hipLaunchKernelGGL((k_moments<3, P, ST>), grid, block, lds, s, A); \
+      break;                                                               \
     }                                                                      \
+    const size_t lds3 =                                                    \
+        mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
     if (mode == 0 && A.a != 0.0)                                           \
       hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds3, s, A);   \
     else if (mode == 0)                                                    \
@@ -488,8 +508,8 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
   return hipGetLastError();
 }
 
-int velocities_per_block(int dim, int order) {
-  if (dim < 3) return kBlock;
+int velocities_per_block(int dim, int order, int precision) {
+  if (dim < 3 || precision == 1) return kBlock;
   return order + 1 <= 2 ? Plane3<1>::VB : Plane3<3>::VB;
 }
 

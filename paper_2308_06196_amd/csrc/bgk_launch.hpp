@@ -13,7 +13,7 @@ namespace bgk {
 
 // Velocities covered by one work-group of the stage kernel (the moment
 // partials are per such chunk).
-int velocities_per_block(int dim, int order);
+int velocities_per_block(int dim, int order, int precision);
 
 // mode 0: fused RK stage (a variant that does not read f^n when a = 0);
 // 1: residual L(f) in FP64; 2: moment partials only.

@@ -240,7 +240,7 @@ Layout layout_of(const bgk_problem* pb) {
   for (int k = 0; k < pb->dim; ++k) L.ns *= pb->order + 1;
   L.nx = L.ne * L.ns;
   L.nv = (int64_t)pb->nvel[0] * pb->nvel[1] * pb->nvel[2];
-  const int vb = velocities_per_block(pb->dim, pb->order);
+  const int vb = velocities_per_block(pb->dim, pb->order, pb->precision);
   L.nchunk = (int)((L.nv + vb - 1) / vb);
   const size_t s = pb->precision == BGK_FP64 ? 8 : 4;
   L.nvb = (L.nv + kVB - 1) / kVB;
