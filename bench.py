@@ -46,12 +46,19 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(csrc: str | None = None) -> str:
+    """Hash of the HIP sources with comments and whitespace removed, so that the
+    stored HBM traffic (profiles/traffic.json) is used only for the kernels it
+    was measured on."""
+    import re
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2308_06196_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2308_06196_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
         if fn.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, fn), "rb").read())
+            src = open(os.path.join(csrc, fn)).read()
+            src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+            src = re.sub(r"//[^\n]*", " ", src)
+            h.update(fn.encode() + b"\0" + " ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

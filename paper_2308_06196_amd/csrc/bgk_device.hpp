@@ -2,15 +2,17 @@
 // hot path (Dzanic & Martinelli, arXiv 2308.06196, Sec. 2 and Sec. 2.1).
 //
 // Data layout in HBM (one solver):
-//   f[elem][node][vel]   storage precision, velocity fastest (coalesced rows
-//                        of nv values per spatial node)
+//   f[elem][vblock][node][64]  storage precision; velocities in blocks of
+//                        kVB = 64 (f_offset), so a wave reads one contiguous
+//                        block per element and node offsets are immediates
+//                        (the ABI exchanges f[elem][node][vel], converted)
 //   partials[chunk][node][5]  FP64 moment partial sums of one stage output,
 //                        one entry per velocity chunk of a work-group (chunk
 //                        major, so a work-group writes one contiguous block)
 //   params[node][8]      FP64 (alpha_0..alpha_4, 1/tau, tau, status) of the
 //                        discretely conservative equilibrium
 //   etab[node][S]        one-dimensional factors of that equilibrium and
-//                        1/tau, in the storage precision of f,
+//                        1/tau, in the precision of the stage arithmetic,
 //                        S = nv1[0] + nv1[1] + nv1[2] + 1:
 //                        g(u) = Ex[bx] Ey[by] Ez[bz] with
 //                        Ex[b] = exp(alpha_0 + alpha_1 u_b + alpha_4 u_b^2/2),
@@ -19,7 +21,9 @@
 //
 // Thread mapping of the stage kernel: one work-group = one element x one
 // chunk of 256 consecutive velocities; one lane = one velocity j and all
-// (p+1)^d nodes of the element, held in registers. The FR operators are
+// (p+1)^d nodes of the element, held in registers (quadrilaterals, and
+// hexahedra in FP32; the plane-split hexahedral kernels are in
+// bgk_device3d.hpp). The FR operators are
 // (p+1)-point contractions along element lines (sum factorisation, VALU);
 // they are far below the FP64/FP32 ridge point, so the kernel is bound by
 // HBM traffic and instruction issue, not by arithmetic peak.
@@ -449,13 +453,6 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Stage kernel: FR transport (volume + upwind inflow-face lift) + BGK
-// relaxation + SSP-RK combine + positivity limiter + next-stage moment
-// partials (MODE 0: a stage that combines with f^n; MODE 3: the first stage,
-// a = 0, which does not read f^n), or the plain residual L(f) in FP64
-// (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
-// ---------------------------------------------------------------------------
 // Waves per SIMD the stage kernel is built for: FP32 quadrilaterals 4, FP64
 // quadrilaterals 3; hexahedra (one lane per velocity with all (p+1)^3 nodes,
 // FP32 storage) 3 at p = 2 and 2 at p = 3 (measured: a few spilled registers
@@ -466,6 +463,13 @@ constexpr int stage_waves() {
   return DIM == 3 && P == 3 ? 2 : DIM == 3 && P == 2 ? 3 : sizeof(CT) == 8 ? 3 : 4;
 }
 
+// ---------------------------------------------------------------------------
+// Stage kernel: FR transport (volume + upwind inflow-face lift) + BGK
+// relaxation + SSP-RK combine + positivity limiter + next-stage moment
+// partials (MODE 0: a stage that combines with f^n; MODE 3: the first stage,
+// a = 0, which does not read f^n), or the plain residual L(f) in FP64
+// (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
+// ---------------------------------------------------------------------------
 template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T>())))

@@ -1,9 +1,12 @@
 // bgk_device3d.hpp -- stage and moment kernels for hexahedral (d = 3)
 // elements on gfx950 (Dzanic & Martinelli, arXiv 2308.06196, Sec. 2.1).
 //
-// A (p+1)^3-node element does not fit one lane's registers, so a group of
-// G lanes (G = 2 for p = 1, 4 for p = 2, 3) shares one velocity and lane g of
-// the group owns the z-plane a_z = g of the element: (p+1)^2 nodes. The x and
+// Plane-split kernels, used where a (p+1)^3-node element does not fit one
+// lane's registers: FP64 storage, and the BF16-increment stages (which hold a
+// second value per neighbour node). FP32 hexahedra run the one-lane-per-
+// velocity k_stage<3, ...> of bgk_device.hpp instead. Here a group of G lanes
+// (G = 2 for p = 1, 4 for p = 2, 3) shares one velocity and lane g of the
+// group owns the z-plane a_z = g of the element: (p+1)^2 nodes. The x and
 // y operators are lane-local exactly as for quadrilaterals; the z-derivative
 // and the z-face traces need the other planes of the same column, which come
 // from the other lanes of the group by DPP quad permutations (no LDS, no
