@@ -480,3 +480,46 @@ def test_bf16_fields_and_state_buffers(torch):
     assert ei.value.status == 2
     b.close()
     sb.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_residual_matches_oracle(torch, name):
+    """FP32 storage and arithmetic (hexahedra on the one-lane-per-velocity
+    kernel): the residual of a state away from equilibrium (amplitude 0.3, so
+    that the collision term is not a difference of nearly equal values) within
+    1e-5 of max|T| + max|C|."""
+    pb, kind = CASES[name]
+    _say("residual-fp32", name)
+    f = initial_state(pb, kind, seed=5, amp=0.3)
+    pr = oracle_problem(pb)
+    s = solver(pb, precision=1)
+    r = s.residual(dev(torch, f)).cpu().numpy()
+    L, _ = orc.residual(pr, f)
+    scale = np.abs(orc.transport(pr, f)).max() + np.abs(orc.collision(pr, f)[0]).max()
+    err = float(np.abs(r - L).max() / scale)
+    print(f"fp32 residual {name}: {err:.2e}")
+    assert err < 1e-5, err
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_hexahedra_specular_walls(torch, order):
+    """A closed 3-D box (specular walls on all six faces: the exterior trace is
+    the own trace at the mirrored velocity): residual and three RK3 steps
+    against the oracle, FP64 (plane-split kernel) and FP32 (one lane per
+    velocity)."""
+    pb = dict(wl.tgv3d(n=2, order=order, nv1=6), bc=[(1, 1)] * 3)
+    _say("hex-specular", order)
+    pr = oracle_problem(pb)
+    f0 = initial_state(pb, "tgv3d", seed=11, amp=0.2)
+    dt = orc.stable_dt(pr, f0, 0.1)
+    L, _ = orc.residual(pr, f0)
+    scale = np.abs(orc.transport(pr, f0)).max() + np.abs(orc.collision(pr, f0)[0]).max()
+    f_orc, _ = orc.rk3_step(pr, f0, dt, 3)
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        s = solver(pb, precision=prec)
+        r = s.residual(dev(torch, f0)).cpu().numpy()
+        assert np.abs(r - L).max() / scale < tol, prec
+        s.set_state(dev(torch, f0))
+        s.rk3_step(dt, 3)
+        assert rel_max(s.get_state().cpu().numpy(), f_orc) < tol, prec
+        s.diagnostics()
