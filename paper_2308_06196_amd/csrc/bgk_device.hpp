@@ -35,7 +35,6 @@
 namespace bgk {
 
 constexpr int kMaxN1 = 4;            // p <= 3
-constexpr int kMaxNS = 64;           // (p+1)^d <= 64
 constexpr int kBlock = 256;          // velocities per work-group
 constexpr int kNumXCD = 8;           // MI355X: 8 accelerator complex dies
 constexpr int kMaxTabBytes = 65536;  // LDS for one element's equilibrium factors

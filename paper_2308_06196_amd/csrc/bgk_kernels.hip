@@ -308,7 +308,6 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const 
 template <int DIM, int P, typename ST>
 __global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
   constexpr int N1 = P + 1;
-  constexpr int NS = ipow(N1, DIM);
   constexpr int NF = ipow(N1, DIM - 1);
   __shared__ double red[kBlock / 64][NF];
   const DevGeom& g = W.g;
