@@ -62,14 +62,12 @@ __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
 
 // All-reduce of one FP64 value over the T lanes of a team (T = 16: one DPP
 // row, partners lane ^ 8, the mirror inside 8 lanes, lane ^ 2, lane ^ 1;
-// T = 4: one quad). Each step pairs lanes symmetrically, so every lane ends
+// T = 8 from the mirror on; T = 4: one quad). Each step pairs lanes symmetrically, so every lane ends
 // with the same bits.
 template <int T>
 __device__ __forceinline__ double team_sum(double x) {
-  if constexpr (T == 16) {
-    x += dpp_partner<8>(x);
-    x += dpp_partner<4>(x);
-  }
+  if constexpr (T == 16) x += dpp_partner<8>(x);
+  if constexpr (T >= 8) x += dpp_partner<4>(x);
   x += dpp_partner<2>(x);
   x += dpp_partner<1>(x);
   return x;
@@ -546,7 +544,9 @@ hipError_t launch_wall(int precision, const WallArgs& W, hipStream_t s) {
 }
 
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
-  if (A.g.nx >= 65536)
+  // teams of 4 lanes per node once there are enough nodes to fill the GPU
+  // (measured on 16,384 nodes: 0.045 ms against 0.076 ms with 16 lanes)
+  if (A.g.nx >= 8192)
     hipLaunchKernelGGL(k_newton<4>, dim3(grid_of(A.g.nx * 4, 256)), dim3(256), 0, s, A);
   else
     hipLaunchKernelGGL(k_newton<16>, dim3(grid_of(A.g.nx * 16, 256)), dim3(256), 0, s, A);
