@@ -50,6 +50,15 @@ struct DevGeom {
   int32_t nchunk;
   double vlo[3], du[3];
   double scale[3];  // 2 / h_k
+  // Internal velocity order (slots): the velocities are grouped by the signs
+  // of their transported components, octant o = s0 + 2 s1 + 4 s2 after
+  // octant, lexicographic (component 0 fastest) inside an octant. vsplit[k]
+  // is the number of nodes with u_k <= 0 on a transported axis (0 on the
+  // others: a single half), voct[o] the first slot of octant o (voct[8] = nv).
+  // Every upwind choice is then uniform over runs of many slots, so a wave's
+  // neighbour loads read whole cache lines of one element.
+  int32_t vsplit[3];
+  int32_t voct[9];
 };
 
 // Internal state layout: f[element][velocity block][node][kVB], blocks of
@@ -197,12 +206,76 @@ struct Vel {
   double w;  // trapezoid weight
 };
 
+// Slot order of a velocity grid (g.dim, nv1, vlo, du set): with octants, the
+// split of transported axis k is the number of nodes with u_k <= 0, by the
+// same u_k = vlo_k + b du_k > 0 test the stage kernels make; without, every
+// split is 0 and the slots are the lexicographic indices.
+inline void set_velocity_slots(DevGeom& g, bool octants) {
+  for (int k = 0; k < 3; ++k) {
+    int m = 0;
+    if (octants && k < g.dim)
+      while (m < g.nv1[k] && !(g.vlo[k] + m * g.du[k] > 0.0)) ++m;
+    g.vsplit[k] = m;
+  }
+  int off = 0;
+  for (int o = 0; o < 8; ++o) {
+    g.voct[o] = off;
+    int sz = 1;
+    for (int k = 0; k < 3; ++k) sz *= (o >> k) & 1 ? g.nv1[k] - g.vsplit[k] : g.vsplit[k];
+    off += sz;
+  }
+  g.voct[8] = off;  // nv
+}
+
+// Slot of the velocity with node indices b (the order described at DevGeom).
+__host__ __device__ __forceinline__ int vel_slot(const DevGeom& g, const int (&b)[3]) {
+  int o = 0, l[3], n[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int hi = b[k] >= g.vsplit[k] ? 1 : 0;
+    o |= hi << k;
+    l[k] = b[k] - (hi ? g.vsplit[k] : 0);
+    n[k] = hi ? g.nv1[k] - g.vsplit[k] : g.vsplit[k];
+  }
+  return g.voct[o] + l[0] + n[0] * (l[1] + n[1] * l[2]);
+}
+
+// Slot of canonical velocity index jc = b0 + N0 (b1 + N1 b2).
+__host__ __device__ __forceinline__ int vel_slot_of_canonical(const DevGeom& g, int jc) {
+  const int r = jc / g.nv1[0];
+  const int b[3] = {jc - r * g.nv1[0], r % g.nv1[1], r / g.nv1[1]};
+  return vel_slot(g, b);
+}
+
+// Node indices b of slot j (the inverse of vel_slot).
+__host__ __device__ __forceinline__ void slot_nodes(const DevGeom& g, int j, int (&b)[3]) {
+  // octant: the last one starting at or before j (empty octants start where
+  // the next one does, so they are never picked)
+  int o = 0;
+#pragma unroll
+  for (int q = 1; q < 8; ++q) o = j >= g.voct[q] ? q : o;
+  int n[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] = (o >> k) & 1 ? g.nv1[k] - g.vsplit[k] : g.vsplit[k];
+  const int loc = j - g.voct[o], r = loc / n[0], l2 = r / n[1];
+  const int l[3] = {loc - r * n[0], r - l2 * n[1], l2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) b[k] = l[k] + ((o >> k) & 1 ? g.vsplit[k] : 0);
+}
+
+// LEX: the grid has a single octant (slots are the lexicographic indices),
+// decoded with the grid's own, uniform divisors.
+template <bool LEX = false>
 __device__ __forceinline__ Vel velocity_of(const DevGeom& g, int j) {
   Vel v;
-  const int r = j / g.nv1[0];
-  v.b[0] = j - r * g.nv1[0];
-  v.b[2] = r / g.nv1[1];
-  v.b[1] = r - v.b[2] * g.nv1[1];
+  if constexpr (LEX) {
+    const int r = j / g.nv1[0];
+    v.b[0] = j - r * g.nv1[0];
+    v.b[2] = r / g.nv1[1];
+    v.b[1] = r - v.b[2] * g.nv1[1];
+  } else {
+    slot_nodes(g, j, v.b);
+  }
   double w = 1.0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -452,14 +525,16 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
   }
 }
 
-// Waves per SIMD the stage kernel is built for: FP32 quadrilaterals 4, FP64
-// quadrilaterals 3; hexahedra (one lane per velocity with all (p+1)^3 nodes,
-// FP32 storage) 3 at p = 2 and 2 at p = 3 (measured: a few spilled registers
-// at p = 3 cost less than halving the waves; at p = 2 four waves' spills cost
-// a third of the time).
-template <int DIM, int P, typename CT>
+// Waves per SIMD the stage kernel is built for: segments and quadrilaterals 5
+// with FP32 storage (6-7 % faster than 4 on the 32^2 p = 3 box), 4 with BF16
+// increments (whose second value per neighbour node spills at 5, which
+// doubled the time), 3 in FP64; hexahedra (one lane per velocity with all
+// (p+1)^3 nodes, FP32 storage) 3 at p = 2 and 2 at p = 3 (measured: a few
+// spilled registers at p = 3 cost less than halving the waves; at p = 2 four
+// waves' spills cost a third of the time).
+template <int DIM, int P, typename CT, bool INC>
 constexpr int stage_waves() {
-  return DIM == 3 && P == 3 ? 2 : DIM == 3 && P == 2 ? 3 : sizeof(CT) == 8 ? 3 : 4;
+  return DIM == 3 && P == 3 ? 2 : DIM == 3 && P == 2 ? 3 : sizeof(CT) == 8 ? 3 : INC ? 4 : 5;
 }
 
 // ---------------------------------------------------------------------------
@@ -471,7 +546,7 @@ constexpr int stage_waves() {
 // ---------------------------------------------------------------------------
 template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T>())))
+    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
     k_stage(const StageArgs A) {
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
@@ -542,7 +617,7 @@ __global__ void __launch_bounds__(kBlock)
     } else if (wall) {
       int bm[3] = {vel.b[0], vel.b[1], vel.b[2]};
       bm[k] = g.nv1[k] - 1 - bm[k];
-      src_j = bm[0] + g.nv1[0] * (bm[1] + g.nv1[1] * bm[2]);
+      src_j = vel_slot(g, bm);
     } else {
       int64_t stride = 1;
       for (int m = 0; m < k; ++m) stride *= g.nelem[m];
@@ -734,7 +809,9 @@ __global__ void __launch_bounds__(kBlock)
   if constexpr (MODE == 1) {
     double* out = (double*)A.out;
     if (valid) {
-      double* oe = out + (e - A.out_e0) * NS * nv + j;
+      // canonical layout: velocity index b0 + N0 (b1 + N1 b2)
+      const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
+      double* oe = out + (e - A.out_e0) * NS * nv + jc;
 #pragma unroll
       for (int i = 0; i < NS; ++i) oe[(int64_t)i * nv] = (double)L[i];
     }

@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kBlock)
   const bool valid = j < nv;
   const bool act = valid && live;
   const int jj = valid ? j : (int)nv - 1;
-  Vel vel = velocity_of(g, jj);
+  Vel vel = velocity_of<sizeof(ST) == 8>(g, jj);  // FP64: lexicographic slots
   if (!act) vel.w = 0.0;
 
   int ek[3];
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kBlock)
     if (wall) {
       int bm[3] = {vel.b[0], vel.b[1], vel.b[2]};
       bm[k] = g.nv1[k] - 1 - bm[k];
-      src_j = bm[0] + g.nv1[0] * (bm[1] + g.nv1[1] * bm[2]);
+      src_j = vel_slot(g, bm);
     } else {
       int64_t stride = 1;
       for (int m = 0; m < k; ++m) stride *= g.nelem[m];
@@ -317,7 +317,8 @@ __global__ void __launch_bounds__(kBlock)
   if constexpr (MODE == 1) {
     double* out = (double*)A.out;
     if (act) {
-      double* oe = out + ((e - A.out_e0) * NS + pl * P2) * nv + j;
+      const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
+      double* oe = out + ((e - A.out_e0) * NS + pl * P2) * nv + jc;
 #pragma unroll
       for (int q = 0; q < P2; ++q) oe[(int64_t)q * nv] = (double)L[q];
     }
@@ -411,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
   const int j = chunk * VB + (int)threadIdx.x / G;
   const bool valid = j < nv;
   const int jj = valid ? j : (int)nv - 1;
-  Vel vel = velocity_of(g, jj);
+  Vel vel = velocity_of<sizeof(ST) == 8>(g, jj);  // FP64: lexicographic slots
   if (!(valid && live)) vel.w = 0.0;
   const ST* fe = (const ST*)A.fin + f_offset(g, e, pl * P2, jj);
   CT f[P2];

@@ -395,7 +395,8 @@ __global__ void __launch_bounds__(kBlock) k_maxwellian(const DevGeom g, const do
 }
 
 // Exchange between the canonical FP64 layout f[elem][node][vel] and the
-// internal layout in storage precision: entries i0 .. i0+m-1 of the canonical
+// internal layout in storage precision (velocity blocks, velocities in slot
+// order): entries i0 .. i0+m-1 of the canonical
 // array, held at canon[0 .. m-1] (a staging window or the whole array).
 template <typename DST>
 __global__ void __launch_bounds__(256) k_to_internal(const DevGeom g, const double* canon, DST* f,
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(256) k_to_internal(const DevGeom g, const doub
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, per_e = (int64_t)g.ns * g.nv;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
     const int64_t i = i0 + t, e = i / per_e, r = i - e * per_e, a = r / g.nv;
-    f[f_offset(g, e, (int)a, r - a * g.nv)] = (DST)canon[t];
+    f[f_offset(g, e, (int)a, vel_slot_of_canonical(g, (int)(r - a * g.nv)))] = (DST)canon[t];
   }
 }
 
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(256) k_to_canonical(const DevGeom g, const SRC
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, per_e = (int64_t)g.ns * g.nv;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
     const int64_t i = i0 + t, e = i / per_e, r = i - e * per_e, a = r / g.nv;
-    canon[t] = (double)f[f_offset(g, e, (int)a, r - a * g.nv)];
+    canon[t] = (double)f[f_offset(g, e, (int)a, vel_slot_of_canonical(g, (int)(r - a * g.nv)))];
   }
 }
 
@@ -481,6 +482,8 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
         hipLaunchKernelGGL((k_moments<3, P, ST>), grid, block, lds, s, A); \
       break;                                                               \
     }                                                                      \
+    /* FP64 plane-split kernels decode lexicographic slots (one octant) */ \
+    if (sizeof(ST) == 8 && A.g.voct[7] != 0) return hipErrorInvalidValue; \
     const size_t lds3 =                                                    \
         mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
     if (mode == 0 && A.a != 0.0)                                           \

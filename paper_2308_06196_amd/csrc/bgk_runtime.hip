@@ -657,6 +657,11 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
   g.nv = s->L.nv;
   g.nvb = s->L.nvb;
   g.nchunk = s->L.nchunk;
+  // velocity slots: octants of the signs of the transported components. FP64
+  // hexahedra keep the lexicographic order (no split): their plane-split
+  // kernels measured 4 % faster with it on the 16^3 x 16^3 Taylor-Green box,
+  // where the FP32 hexahedra ran 6 % faster with the octants.
+  set_velocity_slots(g, !(pb->dim == 3 && pb->precision == BGK_FP64));
   build_ops(g.n1, g.dim, s->op);
   if (pb->dim == 3) brick_order(g.nelem, s->order_host);
   setup_walls(s);
