@@ -99,10 +99,11 @@ def run_gpu(pb, prim_fn, precision, steps, warmup):
     return out
 
 
-def roofline(res, steps):
+def roofline(res, steps, workload):
     """Fused stage kernel: algorithmic bytes = compulsory f traffic, 2s (stage 1:
     read input, write output) + 3s + 3s (stages 2, 3: also read f^n) per DOF,
-    i.e. 8s/3 per DOF per launch on average (BF16 increments: 8 B)."""
+    i.e. 8s/3 per DOF per launch on average (BF16 increments: 8 B). The
+    measured traffic is the one stored for this workload and precision."""
     tm = res["timing"]
     n = tm["stage_launches"]
     if not n:
@@ -113,7 +114,7 @@ def roofline(res, steps):
     traffic = None
     try:
         tr = json.load(open(TRAFFIC_FILE))
-        key = "stage_" + {0: "f64", 1: "f32", 2: "bf16"}[res["precision"]]
+        key = workload + "/stage_" + {0: "f64", 1: "f32", 2: "bf16"}[res["precision"]]
         if tr.get("source_hash") == kernel_source_hash() and key in tr:
             traffic = tr[key]["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
@@ -244,19 +245,19 @@ def main():
         "config": {"workload": desc, "dof": res["dof"], "dt": res["dt"],
                    "newton_it_max": res["diag"]["newton_it_max"],
                    "limiter_hits": res["diag"]["limiter_hits"]},
-        "roofline": roofline(res, a.steps),
+        "roofline": roofline(res, a.steps, a.workload),
     }
     if not a.no_mixed and main_prec == 0:
         mx = run_gpu(pb, prim_fn, 1, a.steps, a.warmup)
         print(f"[bench] {a.workload} fp32-bulk: {mx['value']:.4e} DOF-updates/s, "
               f"{mx['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         line["mixed"] = {"dtype": DTYPE[1], "value": mx["value"],
-                         "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps)}
+                         "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps, a.workload)}
         bf = run_gpu(pb, prim_fn, 2, a.steps, a.warmup)
         print(f"[bench] {a.workload} bf16-increments: {bf['value']:.4e} DOF-updates/s, "
               f"{bf['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         line["mixed_bf16"] = {"dtype": DTYPE[2], "value": bf["value"],
-                              "ms_per_step": bf["ms_per_step"], "roofline": roofline(bf, a.steps)}
+                              "ms_per_step": bf["ms_per_step"], "roofline": roofline(bf, a.steps, a.workload)}
     if a.serving:
         sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")),
                      policy=a.serving_policy, max_members=a.serving_members)
