@@ -1,8 +1,10 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times (the
 fused stage kernels of one SSP-RK3 step): the 2-D periodic box (32x32 elements,
-p=3, 24^3 velocities, 2.3e8 DOF) in FP64 and FP32 storage, and the 3-D
-Taylor-Green box (16^3 elements, p=3, 16^3 velocities, 1.07e9 DOF) in FP32
-storage, each against one full oracle step. The 7.1e9-DOF Mach-2 box is beyond
+p=3, 24^3 velocities, 2.3e8 DOF) and the 3-D Taylor-Green box (16^3 elements,
+p=3, 16^3 velocities, 1.07e9 DOF), each in FP64, FP32 and BF16-increment
+storage against one full oracle step (FP64 1e-12, FP32 1e-5 relative; BF16
+within 1e-5 max|f| + 2 * 2^-8 * dt max|L(f^n)|, the per-step bound of the
+increment rounding used by the smaller parity cases). The 7.1e9-DOF Mach-2 box is beyond
 what the FP64 oracle holds in host memory; there the GPU run is checked by the
 properties that hold at any size (conservation of the FP64 moments, no failed
 equilibrium solve, positivity)."""
@@ -44,23 +46,37 @@ def _full_step(pb, kind, precisions):
         torch.cuda.empty_cache()
     _say("oracle step", pb["nelem"], pb["nvel"])
     f1, _ = orc.rk3_step(pr, f0, dt, 1)
-    return f1, got
+    bf16_bound = None
+    if 2 in precisions:
+        L, _ = orc.residual(pr, f0)
+        bf16_bound = 1e-5 * float(np.abs(f1).max()) + 2.0 * 2.0 ** -8 * dt * float(np.abs(L).max())
+        del L
+    return f1, got, bf16_bound
 
 
-def test_box2d_full_size_step_fp64_and_fp32():
+def _check(f1, got, bf16_bound):
+    for prec, g in got.items():
+        if prec == 0:
+            assert rel_max(g, f1) < 1e-12, "fp64"
+        elif prec == 1:
+            assert rel_max(g, f1) < 1e-5, "fp32"
+        else:
+            err = float(np.abs(g - f1).max())
+            _say("bf16 max error", err, "bound", bf16_bound)
+            assert err < bf16_bound, "bf16"
+
+
+def test_box2d_full_size_step_all_precisions():
     pb = wl.box2d()
     _say("full-size box2d", pb["nelem"], pb["order"], pb["nvel"])
-    f1, got = _full_step(pb, "box2d", (0, 1))
-    assert rel_max(got[0], f1) < 1e-12
-    assert rel_max(got[1], f1) < 1e-5
+    _check(*_full_step(pb, "box2d", (0, 1, 2)))
 
 
 @pytest.mark.timeout(600)
-def test_tgv3d_full_size_step_fp32():
+def test_tgv3d_full_size_step_all_precisions():
     pb = wl.tgv3d()
     _say("full-size tgv3d", pb["nelem"], pb["order"], pb["nvel"])
-    f1, got = _full_step(pb, "tgv3d", (1,))
-    assert rel_max(got[1], f1) < 1e-5
+    _check(*_full_step(pb, "tgv3d", (1, 0, 2)))
 
 
 def test_mach2_full_size_fp32_properties():
