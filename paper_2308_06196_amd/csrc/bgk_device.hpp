@@ -20,7 +20,7 @@
 //                        the last entry of a row is 1/tau of the node
 //
 // Thread mapping of the stage kernel: one work-group = one element x one
-// chunk of 256 consecutive velocities; one lane = one velocity j and all
+// chunk of 256 consecutive velocity slots; one lane = one velocity slot j and all
 // (p+1)^d nodes of the element, held in registers (quadrilaterals, and
 // hexahedra in FP32; the plane-split hexahedral kernels are in
 // bgk_device3d.hpp). The FR operators are
@@ -62,11 +62,12 @@ struct DevGeom {
 };
 
 // Internal state layout: f[element][velocity block][node][kVB], blocks of
-// kVB consecutive velocities (the last one padded). The values one wave reads
+// kVB consecutive velocity slots (the slot order is described at DevGeom; the
+// last block padded). The values one wave reads
 // for one node are kVB consecutive entries and the nodes of an element are kVB
 // entries apart, so a wave streams one contiguous block per element and node
 // offsets fit in the load instructions. Offset of (element e, node a of the
-// element, velocity j).
+// element, velocity slot j).
 constexpr int kVB = 64;
 __host__ __device__ __forceinline__ int64_t f_offset(const DevGeom& g, int64_t e, int a,
                                                      int64_t j) {
@@ -198,7 +199,7 @@ __device__ __forceinline__ T quad_xor(T x) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-lane velocity of velocity index j (32-bit index arithmetic).
+// Per-lane velocity of velocity slot j (32-bit index arithmetic).
 // ---------------------------------------------------------------------------
 struct Vel {
   int b[3];

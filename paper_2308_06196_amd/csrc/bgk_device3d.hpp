@@ -10,7 +10,7 @@
 // y operators are lane-local exactly as for quadrilaterals; the z-derivative
 // and the z-face traces need the other planes of the same column, which come
 // from the other lanes of the group by DPP quad permutations (no LDS, no
-// barriers). A work-group of 256 lanes covers 256 / G consecutive velocities
+// barriers). A work-group of 256 lanes covers 256 / G consecutive velocity slots
 // of one element. Lanes with g >= p+1 (p = 2) load nothing and store nothing.
 #pragma once
 
