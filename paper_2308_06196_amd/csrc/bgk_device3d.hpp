@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kBlock)
   } else if constexpr (MODE == 0) {
     const ST* fn = (const ST*)A.fn + f_offset(g, e, pl * P2, jj);
 #pragma unroll
-    for (int q = 0; q < P2; ++q) fnv[q] = (CT)fn[q * kVB];
+    for (int q = 0; q < P2; ++q) fnv[q] = (CT)__builtin_nontemporal_load(&fn[q * kVB]);  // streams: see k_stage
   }
 
   if (A.collide) {
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(kBlock)
         if (act) {
           ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);
 #pragma unroll
-          for (int q = 0; q < P2; ++q) oe[q * kVB] = (ST)o[q];
+          for (int q = 0; q < P2; ++q) __builtin_nontemporal_store((ST)o[q], &oe[q * kVB]);
         }
       } else {
         uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, pl * P2, jj);
@@ -377,14 +377,14 @@ __global__ void __launch_bounds__(kBlock)
         for (int q = 0; q < P2; ++q) {
           const CT base = MODE == 0 ? fnv[q] : f[q];
           const uint16_t h = f32_bf16(o[q] - base);
-          if (act) oe[q * kVB] = h;
+          if (act) __builtin_nontemporal_store(h, &oe[q * kVB]);
           o[q] = base + bf16_f32(h);
         }
       }
     } else if (act) {
       ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);
 #pragma unroll
-      for (int q = 0; q < P2; ++q) oe[q * kVB] = (ST)o[q];
+      for (int q = 0; q < P2; ++q) __builtin_nontemporal_store((ST)o[q], &oe[q * kVB]);
     }
     // moment partials on the matrix cores; the staging area reuses the
     // equilibrium rows' LDS once every wave is done with them
