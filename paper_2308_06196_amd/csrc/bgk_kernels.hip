@@ -62,13 +62,13 @@ __device__ static int chol5_solve(double J[5][5], const double* b, double* x) {
 
 // All-reduce of one FP64 value over the T lanes of a team (T = 16: one DPP
 // row, partners lane ^ 8, the mirror inside 8 lanes, lane ^ 2, lane ^ 1;
-// T = 8 from the mirror on; T = 4: one quad). Each step pairs lanes symmetrically, so every lane ends
-// with the same bits.
+// T = 8 from the mirror on; T = 4: one quad; T = 2: a lane pair). Each step
+// pairs lanes symmetrically, so every lane ends with the same bits.
 template <int T>
 __device__ __forceinline__ double team_sum(double x) {
   if constexpr (T == 16) x += dpp_partner<8>(x);
   if constexpr (T >= 8) x += dpp_partner<4>(x);
-  x += dpp_partner<2>(x);
+  if constexpr (T >= 4) x += dpp_partner<2>(x);
   x += dpp_partner<1>(x);
   return x;
 }
@@ -76,8 +76,8 @@ __device__ __forceinline__ double team_sum(double x) {
 // One team of kTeam lanes per spatial node. The lanes split the velocity
 // chunks of the moment partials and the nodes of each one-dimensional sum;
 // the 5x5 solve is repeated identically in every lane of the team. Large
-// meshes use 4-lane teams (less redundant solve work), small ones 16-lane
-// teams (enough waves to fill the device).
+// meshes use 2- or 4-lane teams (less redundant solve work), small ones
+// 16-lane teams (enough waves to fill the device).
 template <int kTeam>
 __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   const DevGeom& g = A.g;
@@ -548,8 +548,12 @@ hipError_t launch_wall(int precision, const WallArgs& W, hipStream_t s) {
 
 hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
   // teams of 4 lanes per node once there are enough nodes to fill the GPU
-  // (measured on 16,384 nodes: 0.045 ms against 0.076 ms with 16 lanes)
-  if (A.g.nx >= 8192)
+  // (measured on 16,384 nodes: 0.045 ms against 0.076 ms with 16 lanes and
+  // 0.047 ms with 2), of 2 lanes on large meshes (262,144 nodes: 0.146 ms
+  // against 0.240 ms with 4; 884,736 nodes: 0.54 ms against 0.72 ms)
+  if (A.g.nx >= 131072)
+    hipLaunchKernelGGL(k_newton<2>, dim3(grid_of(A.g.nx * 2, 256)), dim3(256), 0, s, A);
+  else if (A.g.nx >= 8192)
     hipLaunchKernelGGL(k_newton<4>, dim3(grid_of(A.g.nx * 4, 256)), dim3(256), 0, s, A);
   else
     hipLaunchKernelGGL(k_newton<16>, dim3(grid_of(A.g.nx * 16, 256)), dim3(256), 0, s, A);
