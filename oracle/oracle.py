@@ -23,11 +23,15 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bgk_oracle.c")
-_LIB = os.path.join(_HERE, "liborc.so")
+# BGK_ORACLE_LIB names another build of the same source (used to check that
+# planted mistakes in a scratch copy of the oracle fail its pins)
+_LIB = os.environ.get("BGK_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, OpenMP, no fast-math)."""
+    if os.environ.get("BGK_ORACLE_LIB"):
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
