@@ -147,6 +147,12 @@ typedef struct {
   int64_t limiter_hits;   /* (element, velocity) slices contracted         */
   int64_t limiter_bad;    /* slices whose mean was <= 0                    */
   int64_t stages;         /* residual evaluations performed                */
+  int64_t positivity_violations; /* BF16 storage: (element or plane,
+                          * velocity) slices whose stored stage (F plus the
+                          * BF16 increment) has a negative value while the
+                          * stage values themselves are all >= 0; negative
+                          * increments are truncated towards zero, so this
+                          * stays 0 while f^n >= 0                          */
 } bgk_diag;
 
 /* Kernel time inside bgk_rk3_step, measured with HIP events recorded on
@@ -231,6 +237,18 @@ bgk_status bgk_rk3_step(bgk_solver* s, double dt, int32_t nsteps);
  * (Sec. 2 moments with the Sec. 2.1 trapezoid operator), FP64, host or
  * device. Synchronises. */
 bgk_status bgk_moments(bgk_solver* s, double* Q, int32_t where);
+
+/* Discrete moments Cm[nx][5] = M . [C (x) psi] of the BGK collision term
+ * C = (g - f)/tau of the installed state (Sec. 2 relaxation; Sec. 2.1: the
+ * discretely conservative equilibrium makes these vanish), FP64, host or
+ * device per where. C is formed exactly as the stage kernels form it (the
+ * same FP64 equilibrium rows from the same equilibrium solve, the same stored
+ * values of f, the same FP64 arithmetic, in every storage precision), and its
+ * moments are accumulated in FP64 in a fixed order, so Cm measures the
+ * conservation of the collision term the solver applies. Zero when
+ * collisions are off. Synchronises; the next step recomputes the moment
+ * partials of the state. */
+bgk_status bgk_collision_moments(bgk_solver* s, double* Cm, int32_t where);
 
 /* Time step dt = min(cfl / max_j sum_{k<d} |u_jk| / h_k, min_nodes tau) of
  * the installed state. Synchronises. */

@@ -64,7 +64,7 @@ class Timing(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("newton_it_max", C.c_int64), ("newton_fail", C.c_int64),
                 ("limiter_hits", C.c_int64), ("limiter_bad", C.c_int64),
-                ("stages", C.c_int64)]
+                ("stages", C.c_int64), ("positivity_violations", C.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -127,6 +127,7 @@ def lib():
             "bgk_residual": [vp, vp, vp, i32],
             "bgk_rk3_step": [vp, C.c_double, i32],
             "bgk_moments": [vp, vp, i32],
+            "bgk_collision_moments": [vp, vp, i32],
             "bgk_stable_dt": [vp, C.c_double, dp],
             "bgk_diagnostics": [vp, C.POINTER(Diag)],
             "bgk_synchronize": [vp],
@@ -276,6 +277,16 @@ class Solver:
             out = torch.empty((self.nx, 5), dtype=torch.float64, device=self.device)
         p, where, keep = self._arg(out, self.nx * 5)
         _check(lib().bgk_moments(self._s, p, where))
+        return out if isinstance(out, torch.Tensor) else keep
+
+    def collision_moments(self, out=None):
+        """Discrete moments [nx, 5] of the collision term of the installed state,
+        formed as the stage kernels form it (bgk_collision_moments)."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.nx, 5), dtype=torch.float64, device=self.device)
+        p, where, keep = self._arg(out, self.nx * 5)
+        _check(lib().bgk_collision_moments(self._s, p, where))
         return out if isinstance(out, torch.Tensor) else keep
 
     def stable_dt(self, cfl: float) -> float:

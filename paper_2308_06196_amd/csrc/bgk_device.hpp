@@ -84,6 +84,22 @@ struct DevOpsT {
 };
 using DevOps = DevOpsT<double>;
 
+// FR line operators for the matrix-core contraction (FP32 arithmetic). For a
+// velocity with u_k > 0 (pos = 1) the inflow face of an element is its left
+// face, and the transport of one line of p+1 nodes along axis k is
+//   T = a (Dp f_own + E f_nb),   Dp = D - G_in lam_own^T,   E = G_in lam_ext^T,
+// a = u_k 2/h_k, with (lam_own, G_in) = (lamL, GL) where pos and (lamR, GR)
+// otherwise, and lam_ext = lamR where use_right (the upwind neighbour's right
+// trace, or the own trace at a right wall), lamL otherwise: the volume
+// derivative plus the inflow-face correction of the upwind common flux
+// (Sec. 2.1, correction functions recovering nodal DG). Rows and columns
+// beyond p+1 are zero.
+struct alignas(16) LineOps {
+  float Dp[2][4][4];    // [pos][row i][column k]
+  float E[2][2][4][4];  // [pos][use_right][row i][column k]
+};
+constexpr int kLineOpsFloats = (int)(sizeof(LineOps) / sizeof(float));
+
 struct StageArgs {
   DevGeom g;
   DevOps op;
@@ -92,7 +108,7 @@ struct StageArgs {
   const void* fn;   // f^n (storage precision), read when a != 0
   void* out;        // stage output (storage precision), or FP64 residual
   const double* params;
-  const void* etab;      // equilibrium factors, storage precision
+  const double* etab;    // equilibrium factor rows (FP64)
   const int32_t* order;  // traversal order of the elements (null: lexicographic)
   double* partials;
   unsigned long long* diag;  // newton it max, newton fail, lim hits, lim bad, stages
@@ -111,6 +127,7 @@ struct StageArgs {
   // the increment o - F in BF16, or o itself in FP32 when out_full is set
   const uint16_t* din;
   int32_t out_full;
+  LineOps lops;  // FR line operators for the matrix-core contraction (FP32)
 };
 
 // BF16 <-> FP32: the upper half of the FP32 bit pattern; rounding to nearest,
@@ -143,12 +160,12 @@ struct NewtonArgs {
   DevGeom g;
   const double* partials;
   double* params;
-  void* etab;  // equilibrium factors, written in the storage precision
+  double* etab;  // equilibrium factor rows (FP64)
   double* Q;   // optional [nx][5] output of the reduced moments
   unsigned long long* diag;
   double gamma, mu_ref, theta_ref, omega, tol;
   double sutherland;  // > 0: Sutherland constant (power law otherwise)
-  int32_t maxit, collide, etab_f32;
+  int32_t maxit, collide;
   int32_t continuous;  // 1: continuous Maxwellian of (rho, U, theta), no Newton solve
 };
 
@@ -377,12 +394,12 @@ __device__ __forceinline__ const DevOpsT<CT>& ops_of(const StageArgs& A) {
   else return A.opf;
 }
 
-// Equilibrium rows from index kU * kBlock on (the first kU * kBlock entries
-// are loaded with the bulk loads) -> LDS.
-template <int kU, typename ST, typename CT>
-__device__ __forceinline__ void table_rest(CT* tab, const ST* et, int ntab) {
+// Equilibrium rows (FP64) from index kU * kBlock on (the first kU * kBlock
+// entries are loaded with the bulk loads) -> LDS.
+template <int kU>
+__device__ __forceinline__ void table_rest(double* tab, const double* et, int ntab) {
   for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
-    ST v[kU];
+    double v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = t0 + u * kBlock + (int)threadIdx.x;
@@ -391,7 +408,7 @@ __device__ __forceinline__ void table_rest(CT* tab, const ST* et, int ntab) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = t0 + u * kBlock + (int)threadIdx.x;
-      if (t < ntab) tab[t] = (CT)v[u];
+      if (t < ntab) tab[t] = v[u];
     }
   }
 }
@@ -526,6 +543,92 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
   }
 }
 
+// BGK collision term at one (node, velocity) in FP64 (Sec. 2, C = (g - f)/tau;
+// Sec. 2.1, g the discretely conservative equilibrium): from the node's FP64
+// equilibrium row ti (Ex with exp(alpha_0) and 1/tau folded in, Ey, Ez, then
+// 1/tau at ti[S - 1]) and the velocity's row offsets. Every stage kernel, in
+// every storage precision, forms the collision term with this function, so
+// its discrete moments vanish to FP64 rounding (the conservation the Newton
+// solve of the equilibrium reaches); bgk_collision_moments measures them with
+// the same function.
+__device__ __forceinline__ double collision_term(const double* ti, int bx, int oy, int oz, int S,
+                                                 double f) {
+  return fma(-f, ti[S - 1], ti[bx] * ti[oy] * ti[oz]);
+}
+
+// Stored BF16 increment of a stage value o over the FP32 base F, and the
+// value F + increment that the next stage reads. A non-negative increment is
+// rounded to nearest (ties to even); a negative one is truncated towards zero,
+// so that F + increment >= o up to the FP32 rounding of o - F: where o >= 0
+// and F >= 0 the stored stage is exactly >= 0, since o - F >= -F rounds to a
+// value >= -F and truncation only shrinks it. The stored stages thus keep the
+// positivity the limiter of Sec. 2.1 establishes (rounding to nearest could
+// put F + increment below zero by up to 2^-9 F where the limiter has just
+// lifted a node to zero). Returns the bits.
+__device__ __forceinline__ uint16_t bf16_increment(float o, float base, float& stored) {
+  const float d = o - base;
+  const uint32_t u = __float_as_uint(d);
+  const uint16_t h = (u & 0x80000000u) ? (uint16_t)(u >> 16) : f32_bf16(d);
+  stored = base + bf16_f32(h);
+  return h;
+}
+
+
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// One line on v_mfma_f32_4x4x1_16b_f32: block b of the instruction takes lanes
+// 4b..4b+3 (four velocities); its A operand (4 x 1) comes from those lanes'
+// registers (row i from lane 4b + i), its B operand (1 x 4) and its result
+// column j from lane 4b + j. With A = column k of the operator (row lane & 3,
+// read by every lane from the same table) and B = the lane's own value of node
+// k of the line, the result column of a lane is the operator applied to its
+// own line: a lane-local (p+1)-point contraction, with the blocks of four
+// velocities sharing the operator (the layout was checked on the device with
+// distinct operands in every lane).
+template <int N1>
+__device__ __forceinline__ mfma_f4 line_mfma(const float (&dp)[4], const float (&ev)[4],
+                                             const float (&fl)[N1], const float (&nl)[N1]) {
+  mfma_f4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < N1; ++k) c = __builtin_amdgcn_mfma_f32_4x4x1f32(dp[k], fl[k], c, 0, 0, 0);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) c = __builtin_amdgcn_mfma_f32_4x4x1f32(ev[k], nl[k], c, 0, 0, 0);
+  return c;
+}
+
+// Copy the line operators to this wave's LDS copy (read back through per-lane
+// addresses).
+__device__ __forceinline__ void line_ops_store(LineOps& lo, const LineOps& src) {
+  const int lane = threadIdx.x & 63;
+  const float* s = reinterpret_cast<const float*>(&src);
+  float* d = reinterpret_cast<float*>(&lo);
+  for (int t = lane; t < kLineOpsFloats; t += 64) d[t] = s[t];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Operator columns of this lane's row for table sign sg and trace side ur.
+__device__ __forceinline__ void line_ops_row(const LineOps& lo, int sg, int ur, float (&dp)[4],
+                                             float (&ev)[4]) {
+  const int i = threadIdx.x & 3;
+  const float4 d = *reinterpret_cast<const float4*>(&lo.Dp[sg][i][0]);
+  const float4 e = *reinterpret_cast<const float4*>(&lo.E[sg][ur][i][0]);
+  dp[0] = d.x, dp[1] = d.y, dp[2] = d.z, dp[3] = d.w;
+  ev[0] = e.x, ev[1] = e.y, ev[2] = e.z, ev[3] = e.w;
+}
+
+// True when every aligned group of four lanes of the wave agrees on pos, so
+// that one operator per block serves all its velocities (always the case in
+// the slot order of the grids whose sign octants hold multiples of four
+// velocities).
+__device__ __forceinline__ bool quads_agree(bool pos) {
+  const int v = pos ? 1 : 0;
+  const int a = __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+  const int b = __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+  return __ballot(a != v || b != v) == 0;
+}
+
 // Waves per SIMD the stage kernel is built for: segments and quadrilaterals 5
 // with FP32 storage (6-7 % faster than 4 on the 32^2 p = 3 box), 4 with BF16
 // increments (whose second value per neighbour node spills at 5, which
@@ -543,7 +646,12 @@ constexpr int stage_waves() {
 // relaxation + SSP-RK combine + positivity limiter + next-stage moment
 // partials (MODE 0: a stage that combines with f^n; MODE 3: the first stage,
 // a = 0, which does not read f^n), or the plain residual L(f) in FP64
-// (MODE 1). Dynamic LDS: NS * S values of type CT (equilibrium rows).
+// (MODE 1). Dynamic LDS: NS * S FP64 values (equilibrium rows).
+//
+// FP64 arithmetic runs the line contractions on the VALU. FP32 arithmetic
+// (FP32 storage and BF16 increments) runs them on the matrix cores
+// (line_mfma), with the relaxation term formed in FP64 and added to the FP32
+// stage combination in FP64 before the stored value is rounded.
 // ---------------------------------------------------------------------------
 template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
@@ -551,6 +659,11 @@ __global__ void __launch_bounds__(kBlock)
     k_stage(const StageArgs A) {
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
+  // FR line contractions on the matrix cores for FP32 arithmetic on p = 3
+  // hexahedra (measured 2-4 % faster there); segments, quadrilaterals and
+  // p < 3 hexahedra keep them on the VALU, which measured faster (2-D box:
+  // 0.60 against 0.76 ms per stage; Mach-2 box, p = 2: 20.6 against 21.8 ms)
+  constexpr bool kMfma = sizeof(CT) == 4 && DIM == 3 && P == 3;
   constexpr int N1 = P + 1;
   constexpr int NS = ipow(N1, DIM);
   // the upwind neighbours' nodes are held in registers, one axis at a time,
@@ -559,13 +672,16 @@ __global__ void __launch_bounds__(kBlock)
   constexpr bool kPreload = NS * DIM <= 48;
   __shared__ double red[(kBlock / 64) * part_rows<NS>() * 5];
   __shared__ FaceRows<CT> frows[kBlock / 64];
+  __shared__ LineOps lops[kMfma ? kBlock / 64 : 1];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  CT* tab = reinterpret_cast<CT*>(dyn_lds);
+  double* tab = reinterpret_cast<double*>(dyn_lds);
 
   const DevGeom& g = A.g;
   const DevOpsT<CT>& OP = ops_of<CT>(A);
   FaceRows<CT>& fr = frows[threadIdx.x >> 6];
   face_rows_store<CT, N1>(fr, OP);
+  LineOps& lo = lops[kMfma ? threadIdx.x >> 6 : 0];
+  if constexpr (kMfma) line_ops_store(lo, A.lops);
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
@@ -598,12 +714,15 @@ __global__ void __launch_bounds__(kBlock)
   // (dif[k]; the loads then read the own element and go unused).
   const ST* __restrict__ fin = (const ST*)A.fin;
   const ST* src[DIM];
-  bool pos[DIM], use_right[DIM], dif[DIM];
+  bool pos[DIM], use_right[DIM], dif[DIM], wall_in[DIM][2];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     pos[k] = vel.u[k] * g.scale[k] > 0.0;
     const int nek = sreg(g.nelem[k]);
     const bool wall_lo = sreg(g.bc[k][0]) != 0, wall_hi = sreg(g.bc[k][1]) != 0;
+    // a wall on the inflow side of the element, for either sign of u_k
+    wall_in[k][1] = ek[k] == 0 && wall_lo;
+    wall_in[k][0] = ek[k] == nek - 1 && wall_hi;
     int nk = ek[k] + (pos[k] ? -1 : 1);
     bool wall = false;
     if (nk < 0 || nk >= nek) {
@@ -635,10 +754,10 @@ __global__ void __launch_bounds__(kBlock)
   // 142 instead of 213 VGPRs at p = 3 in FP64, three waves per SIMD); (3) f^n
   // after the transport. Every lane loads (clamped index, no branch): a
   // conditional load makes the compiler wait for it right there.
-  constexpr int kU = 8;
+  constexpr int kU = DIM == 3 ? 4 : 8;
   const int ntab = NS * S;
-  const ST* et = (const ST*)A.etab + node0 * S;
-  ST tv[kU];
+  const double* et = A.etab + node0 * S;
+  double tv[kU];
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -680,7 +799,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
-      if (t < ntab) tab[t] = (CT)tv[u];
+      if (t < ntab) tab[t] = tv[u];
     }
   }
 
@@ -705,18 +824,17 @@ __global__ void __launch_bounds__(kBlock)
         }
       }
     }
-    const CT a = (CT)(vel.u[k] * g.scale[k]);
-    CT lown[N1], lext[N1], Gin[N1];
-    {
-      const CT* ro = fr.r[pos[k] ? 1 : 0];
-      const CT* re = fr.r[use_right[k] ? 0 : 1];
-#pragma unroll
-      for (int bb = 0; bb < N1; ++bb) {
-        lown[bb] = ro[bb];
-        Gin[bb] = ro[kMaxN1 + bb];
-        lext[bb] = re[bb];
+    // value of node i of the upwind (or wall) neighbour on axis k
+    auto nbval = [&](int i) -> CT {
+      if constexpr (kPreload) {
+        return nbv[k][i];
+      } else {
+        CT xv = (CT)src[k][i * kVB];
+        if constexpr (kDin) xv += bf16_f32(din[(src[k] - fin) + i * kVB]);
+        return xv;
       }
-    }
+    };
+    const CT a = (CT)(vel.u[k] * g.scale[k]);
     // diffuse walls of this axis touching the element (uniform)
     const double* rho_lo = nullptr;
     const double* rho_hi = nullptr;
@@ -738,6 +856,47 @@ __global__ void __launch_bounds__(kBlock)
         mw = (CT)(wp[0] * exp(-(d0 * d0 + d1 * d1 + d2 * d2) * wp[1]));
       }
     }
+    if constexpr (kMfma) {
+      if (!dwall) {  // uniform
+        // one pass with each lane's own operators when every block of four
+        // lanes shares the sign of u_k; otherwise one pass per sign, each
+        // applied to the lanes of that sign only
+        const bool uni = quads_agree(pos[k]);
+        const int npass = uni ? 1 : 2;
+        for (int ps = 0; ps < npass; ++ps) {
+          const int sg = uni ? (pos[k] ? 1 : 0) : ps;
+          const int ur = sg ? (wall_in[k][1] ? 0 : 1) : (wall_in[k][0] ? 1 : 0);
+          float dp[4], ev[4];
+          line_ops_row(lo, sg, ur, dp, ev);
+          const CT as = (uni || (pos[k] ? 1 : 0) == sg) ? a : (CT)0;
+#pragma unroll
+          for (int base = 0; base < NS; ++base) {
+            if ((base / S1) % N1 != 0) continue;
+            float fl[N1], nl[N1];
+#pragma unroll
+            for (int bb = 0; bb < N1; ++bb) {
+              fl[bb] = f[base + bb * S1];
+              nl[bb] = nbval(base + bb * S1);
+            }
+            const mfma_f4 c = line_mfma<N1>(dp, ev, fl, nl);
+#pragma unroll
+            for (int ia = 0; ia < N1; ++ia) acc[base + ia * S1] = fmaf(as, c[ia], acc[base + ia * S1]);
+          }
+        }
+        continue;
+      }
+    }
+    CT lown[N1], lext[N1], Gin[N1];
+    {
+      const CT* ro = fr.r[pos[k] ? 1 : 0];
+      const CT* re = fr.r[use_right[k] ? 0 : 1];
+#pragma unroll
+      for (int bb = 0; bb < N1; ++bb) {
+        lown[bb] = ro[bb];
+        Gin[bb] = ro[kMaxN1 + bb];
+        lext[bb] = re[bb];
+      }
+    }
 #pragma unroll
     for (int base = 0; base < NS; ++base) {
       if ((base / S1) % N1 != 0) continue;
@@ -748,14 +907,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int bb = 0; bb < N1; ++bb) {
         own += lown[bb] * line[bb];
-        CT xv;
-        if constexpr (kPreload)
-          xv = nbv[k][base + bb * S1];
-        else {
-          xv = (CT)src[k][(base + bb * S1) * kVB];
-          if constexpr (kDin) xv += bf16_f32(din[(src[k] - fin) + (base + bb * S1) * kVB]);
-        }
-        ext += lext[bb] * xv;
+        ext += lext[bb] * nbval(base + bb * S1);
       }
       if (dwall) {  // uniform: the element touches a diffuse wall of axis k
         // flux point of this line on the wall face
@@ -792,46 +944,56 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < NS; ++i) fnv[i] = (CT)__builtin_nontemporal_load(&fn[i * kVB]);
   }
-  // BGK relaxation towards the discretely conservative equilibrium,
-  // g = Ex[bx] Ey[by] Ez[bz] from the LDS factors
-  CT L[NS];
+  // BGK relaxation towards the discretely conservative equilibrium (FP64
+  // rows from LDS), combined with the transport and the SSP-RK weights. FP32
+  // arithmetic: f - dt T and the RK weights in FP32, the collision term in
+  // FP64, weighted by b dt and added in FP64, then rounded once. The whole
+  // relaxation sits in the one branch that loads the rows (keeping it there
+  // lets the compiler overlap the LDS reads of all nodes without holding them
+  // across the branch).
+  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
+  double* oe1 = nullptr;  // residual output (canonical layout, MODE 1)
+  if constexpr (MODE == 1) {
+    const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
+    oe1 = (double*)A.out + (e - A.out_e0) * NS * nv + jc;
+  }
+  const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
+  const double wc = A.b * A.dt;
+  CT o[NS];
   if (A.collide) {  // uniform; one branch, so the LDS reads of all nodes overlap
-    // rows beyond the first batch (large velocity grids); loaded only now so
+    // rows beyond the first batch (large velocity grids), loaded only now so
     // that their loop does not hold back the waits of the bulk loads
     table_rest<kU>(tab, et, ntab);
     lds_barrier();
-    const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      const CT* ti = tab + i * S;
-      const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
-      L[i] = -acc[i] + (gq - f[i]) * ti[S - 1];
+      const double c = collision_term(tab + i * S, vel.b[0], oy, oz, S, (double)f[i]);
+      if constexpr (MODE == 1) {
+        if (valid) oe1[(int64_t)i * nv] = c - (double)acc[i];
+      } else if constexpr (kMfma) {
+        const CT r = fmaf(-dt, acc[i], f[i]);
+        const CT b32 = MODE == 0 ? fmaf(ca, fnv[i], cb * r) : cb * r;
+        o[i] = (CT)fma(wc, c, (double)b32);
+      } else {
+        const CT L = -acc[i] + (CT)c;
+        o[i] = MODE == 0 ? ca * fnv[i] + cb * (f[i] + dt * L) : cb * (f[i] + dt * L);
+      }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) L[i] = -acc[i];
+    for (int i = 0; i < NS; ++i) {
+      if constexpr (MODE == 1) {
+        if (valid) oe1[(int64_t)i * nv] = -(double)acc[i];
+      } else {
+        const CT L = -acc[i];
+        o[i] = MODE == 0 ? ca * fnv[i] + cb * (f[i] + dt * L) : cb * (f[i] + dt * L);
+      }
+    }
   }
 
   if constexpr (MODE == 1) {
-    double* out = (double*)A.out;
-    if (valid) {
-      // canonical layout: velocity index b0 + N0 (b1 + N1 b2)
-      const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
-      double* oe = out + (e - A.out_e0) * NS * nv + jc;
-#pragma unroll
-      for (int i = 0; i < NS; ++i) oe[(int64_t)i * nv] = (double)L[i];
-    }
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
   } else {
-    const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
-    CT o[NS];
-    if constexpr (MODE == 0) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) o[i] = ca * fnv[i] + cb * (f[i] + dt * L[i]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) o[i] = cb * (f[i] + dt * L[i]);
-    }
     if (A.limiter) {
       CT fmin = o[0];
 #pragma unroll
@@ -862,13 +1024,20 @@ __global__ void __launch_bounds__(kBlock)
         }
       } else {
         uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, 0, jj);
+        float omin = INFINITY, smin = INFINITY;  // stage values / stored values
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const CT base = MODE == 0 ? fnv[i] : f[i];
-          const uint16_t h = f32_bf16(o[i] - base);
+          float stored;
+          const uint16_t h = bf16_increment(o[i], base, stored);
           if (valid) __builtin_nontemporal_store(h, &oe[i * kVB]);
-          o[i] = base + bf16_f32(h);
+          omin = fminf(omin, o[i]);
+          smin = fminf(smin, stored);
+          o[i] = stored;
         }
+        // slices whose stored stage is negative where the stage itself is not
+        const unsigned long long nviol = __popcll(__ballot(valid && smin < 0.0f && !(omin < 0.0f)));
+        if ((threadIdx.x & 63) == 0 && nviol) atomicAdd(&A.diag[5], nviol);
       }
     } else {
       ST* out = (ST*)A.out;

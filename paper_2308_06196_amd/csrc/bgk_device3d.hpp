@@ -107,16 +107,20 @@ __global__ void __launch_bounds__(kBlock)
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
+  constexpr bool kMfma = sizeof(CT) == 4;
   constexpr int N1 = PL::N1, G = PL::G, VB = PL::VB, P2 = PL::P2, NS = PL::NS;
   __shared__ double red[(kBlock / 64) * NS * 5];
   __shared__ FaceRows<CT> frows[kBlock / 64];
+  __shared__ LineOps lops[kMfma ? kBlock / 64 : 1];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  CT* tab = reinterpret_cast<CT*>(dyn_lds);
+  double* tab = reinterpret_cast<double*>(dyn_lds);
 
   const DevGeom& g = A.g;
   const DevOpsT<CT>& OP = ops_of<CT>(A);
   FaceRows<CT>& fr = frows[threadIdx.x >> 6];
   face_rows_store<CT, N1, true>(fr, OP);
+  LineOps& lo = lops[kMfma ? threadIdx.x >> 6 : 0];
+  if constexpr (kMfma) line_ops_store(lo, A.lops);
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
@@ -145,12 +149,14 @@ __global__ void __launch_bounds__(kBlock)
   }
   const ST* __restrict__ fin = (const ST*)A.fin;
   const ST* src[3];
-  bool pos[3], use_right[3];
+  bool pos[3], use_right[3], wall_in[3][2];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     pos[k] = vel.u[k] * g.scale[k] > 0.0;
     const int nek = sreg(g.nelem[k]);
     const bool wall_lo = sreg(g.bc[k][0]) != 0, wall_hi = sreg(g.bc[k][1]) != 0;
+    wall_in[k][1] = ek[k] == 0 && wall_lo;
+    wall_in[k][0] = ek[k] == nek - 1 && wall_hi;
     int nk = ek[k] + (pos[k] ? -1 : 1);
     bool wall = false;
     if (nk < 0 || nk >= nek) {
@@ -174,10 +180,12 @@ __global__ void __launch_bounds__(kBlock)
 
   // loads: equilibrium rows (first batch), own plane, the x-, y- and
   // z-neighbours' planes, f^n plane
-  constexpr int kU = P == 3 ? 16 : 8;  // first batch: 16^3 grids at p = 3
+  // first batch of row loads (FP64 values: 8 x 256 for FP32 arithmetic, whose
+  // registers are scarcer; 16 x 256 covers the 16^3 grid at p = 3 in FP64)
+  constexpr int kU = P == 3 && !kMfma ? 16 : 8;
   const int ntab = NS * S;
-  const ST* et = (const ST*)A.etab + node0 * S;
-  ST tv[kU];
+  const double* et = A.etab + node0 * S;
+  double tv[kU];
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {  // clamped, unconditional loads
@@ -221,7 +229,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
-      if (t < ntab) tab[t] = (CT)tv[u];
+      if (t < ntab) tab[t] = tv[u];
     }
   }
 
@@ -229,11 +237,38 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int q = 0; q < P2; ++q) acc[q] = (CT)0;
 
-  // x and y: lines inside the plane, lane-local
+  // x and y: lines inside the plane, lane-local (FP32 arithmetic on the matrix
+  // cores, see line_mfma: a block of four lanes is one velocity's planes for
+  // p >= 2, two velocities for p = 1)
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int S1 = k == 0 ? 1 : N1;
     const CT a = (CT)(vel.u[k] * g.scale[k]);
+    if constexpr (kMfma) {
+      const bool uni = quads_agree(pos[k]);
+      const int npass = uni ? 1 : 2;
+      for (int ps = 0; ps < npass; ++ps) {
+        const int sg = uni ? (pos[k] ? 1 : 0) : ps;
+        const int ur = sg ? (wall_in[k][1] ? 0 : 1) : (wall_in[k][0] ? 1 : 0);
+        float dp[4], ev[4];
+        line_ops_row(lo, sg, ur, dp, ev);
+        const CT as = (uni || (pos[k] ? 1 : 0) == sg) ? a : (CT)0;
+#pragma unroll
+        for (int base = 0; base < P2; ++base) {
+          if ((base / S1) % N1 != 0) continue;
+          float fl[N1], nl[N1];
+#pragma unroll
+          for (int bb = 0; bb < N1; ++bb) {
+            fl[bb] = f[base + bb * S1];
+            nl[bb] = nb[k][base + bb * S1];
+          }
+          const mfma_f4 c = line_mfma<N1>(dp, ev, fl, nl);
+#pragma unroll
+          for (int ia = 0; ia < N1; ++ia) acc[base + ia * S1] = fmaf(as, c[ia], acc[base + ia * S1]);
+        }
+      }
+      continue;
+    }
     CT lown[N1], lext[N1], Gin[N1];
     {
       const CT* ro = fr.r[pos[k] ? 1 : 0];
@@ -298,41 +333,51 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
 
-  CT L[P2];
-  if (A.collide) {  // uniform; one branch, so the LDS reads of all nodes overlap
-    table_rest<kU>(tab, et, ntab);  // rows beyond the first batch
+  // relaxation and RK combination (as in k_stage: the collision term in
+  // FP64 from the FP64 rows; FP32 arithmetic adds it to the FP32 combination
+  // in FP64), all inside the branch that loads the rows
+  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
+  const double* tp = tab + pl * P2 * S;  // rows of this lane's plane
+  double* oe1 = nullptr;                 // residual output (MODE 1)
+  if constexpr (MODE == 1) {
+    const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
+    oe1 = (double*)A.out + ((e - A.out_e0) * NS + pl * P2) * nv + jc;
+  }
+  const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
+  const double wc = A.b * A.dt;
+  CT o[P2];
+  if (A.collide) {  // uniform: rows beyond the first batch, then the relaxation
+    table_rest<kU>(tab, et, ntab);
     lds_barrier();
-    const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
 #pragma unroll
     for (int q = 0; q < P2; ++q) {
-      const CT* ti = tab + (pl * P2 + q) * S;
-      const CT gq = ti[vel.b[0]] * ti[oy] * ti[oz];
-      L[q] = -acc[q] + (gq - f[q]) * ti[S - 1];
+      const double c = collision_term(tp + q * S, vel.b[0], oy, oz, S, (double)f[q]);
+      if constexpr (MODE == 1) {
+        if (act) oe1[(int64_t)q * nv] = c - (double)acc[q];
+      } else if constexpr (kMfma) {
+        const CT r = fmaf(-dt, acc[q], f[q]);
+        const CT b32 = MODE == 0 ? fmaf(ca, fnv[q], cb * r) : cb * r;
+        o[q] = (CT)fma(wc, c, (double)b32);
+      } else {
+        const CT L = -acc[q] + (CT)c;
+        o[q] = MODE == 0 ? ca * fnv[q] + cb * (f[q] + dt * L) : cb * (f[q] + dt * L);
+      }
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < P2; ++q) L[q] = -acc[q];
+    for (int q = 0; q < P2; ++q) {
+      if constexpr (MODE == 1) {
+        if (act) oe1[(int64_t)q * nv] = -(double)acc[q];
+      } else {
+        const CT L = -acc[q];
+        o[q] = MODE == 0 ? ca * fnv[q] + cb * (f[q] + dt * L) : cb * (f[q] + dt * L);
+      }
+    }
   }
 
   if constexpr (MODE == 1) {
-    double* out = (double*)A.out;
-    if (act) {
-      const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
-      double* oe = out + ((e - A.out_e0) * NS + pl * P2) * nv + jc;
-#pragma unroll
-      for (int q = 0; q < P2; ++q) oe[(int64_t)q * nv] = (double)L[q];
-    }
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
   } else {
-    const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
-    CT o[P2];
-    if constexpr (MODE == 0) {
-#pragma unroll
-      for (int q = 0; q < P2; ++q) o[q] = ca * fnv[q] + cb * (f[q] + dt * L[q]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < P2; ++q) o[q] = cb * (f[q] + dt * L[q]);
-    }
     if (A.limiter) {
       // element mean and minimum over all planes of the velocity
       CT wz = (CT)0;  // Gauss weight of this lane's plane
@@ -373,13 +418,21 @@ __global__ void __launch_bounds__(kBlock)
         }
       } else {
         uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, pl * P2, jj);
+        float omin = INFINITY, smin = INFINITY;  // stage values / stored values
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
           const CT base = MODE == 0 ? fnv[q] : f[q];
-          const uint16_t h = f32_bf16(o[q] - base);
+          float stored;
+          const uint16_t h = bf16_increment(o[q], base, stored);
           if (act) __builtin_nontemporal_store(h, &oe[q * kVB]);
-          o[q] = base + bf16_f32(h);
+          omin = fminf(omin, o[q]);
+          smin = fminf(smin, stored);
+          o[q] = stored;
         }
+        // (velocity, plane) pairs whose stored stage is negative where the
+        // stage itself is not
+        const unsigned long long nviol = __popcll(__ballot(act && smin < 0.0f && !(omin < 0.0f)));
+        if ((threadIdx.x & 63) == 0 && nviol) atomicAdd(&A.diag[5], nviol);
       }
     } else if (act) {
       ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);

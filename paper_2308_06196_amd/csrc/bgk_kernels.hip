@@ -232,8 +232,16 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
 #pragma unroll
     for (int a = 0; a < 5; ++a) al[a] = __builtin_nan("");
   }
-  // one-dimensional factors of the equilibrium, exp(alpha_0) folded into x,
-  // stored in the storage precision of f
+  // relaxation time tau = mu / P (Sec. 2) with mu from the temperature law
+  const double tr = th / A.theta_ref;
+  const double mu = A.sutherland > 0.0
+                        ? A.mu_ref * tr * sqrt(tr) * (A.theta_ref + A.sutherland) / (th + A.sutherland)
+                        : A.mu_ref * pow(tr, A.omega);
+  const double itau = P / mu;  // 1 / tau
+  // one-dimensional factors of the equilibrium in FP64 for every storage
+  // precision: exp(alpha_0) and 1/tau folded into x, so that the stage kernels
+  // form the collision term as Ex[bx] Ey[by] Ez[bz] - f / tau
+  double* row = (double*)A.etab + node * g.tabw;
   int off = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -243,30 +251,18 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
       for (int b = r; b < N; b += kTeam) {
         const double u = g.vlo[c] + b * g.du[c];
         const double v = exp(a0 + al[1 + c] * u + al[4] * (0.5 * u * u));
-        if (A.etab_f32)
-          ((float*)A.etab)[node * g.tabw + off + b] = (float)v;
-        else
-          ((double*)A.etab)[node * g.tabw + off + b] = v;
+        row[off + b] = c == 0 ? v * itau : v;
       }
     }
     off += N;
   }
   if (r == 0 && active) {
-    const double tr = th / A.theta_ref;
-    const double mu = A.sutherland > 0.0
-                          ? A.mu_ref * tr * sqrt(tr) * (A.theta_ref + A.sutherland) / (th + A.sutherland)
-                          : A.mu_ref * pow(tr, A.omega);
-    const double tau = mu / P;
 #pragma unroll
     for (int a = 0; a < 5; ++a) out[a] = al[a];
-    out[5] = 1.0 / tau;
-    out[6] = tau;
+    out[5] = itau;
+    out[6] = 1.0 / itau;
     out[7] = (double)status;
-    // 1/tau closes the node's row of the factor table
-    if (A.etab_f32)
-      ((float*)A.etab)[node * g.tabw + off] = (float)(1.0 / tau);
-    else
-      ((double*)A.etab)[node * g.tabw + off] = 1.0 / tau;
+    row[off] = itau;  // 1/tau closes the node's row
   }
   // counters: one atomic per wave (the four teams of a wave reduced first)
   int itw = active ? iters : 0;
@@ -290,6 +286,51 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const 
     for (int m = 0; m < 5; ++m) q[m] += pp[(int64_t)c * g.nx * 5 + m];
 #pragma unroll
   for (int m = 0; m < 5; ++m) Q[node * 5 + m] = q[m];
+}
+
+// Discrete moments of the collision term of a stored state, per node and
+// chunk of kBlock velocities: sum_j w_j psi_j C_j with C_j formed by
+// collision_term from the FP64 equilibrium rows and the stored values, as in
+// the stage kernels. One work-group = one element x one chunk; lanes are
+// summed by an xor butterfly and the four waves in a fixed order.
+template <typename ST>
+__global__ void __launch_bounds__(kBlock) k_collision_moments(const StageArgs A, int nchunk) {
+  __shared__ double red[kBlock / 64][5];
+  const DevGeom& g = A.g;
+  const int64_t e = (int64_t)blockIdx.x / nchunk;
+  const int chunk = (int)(blockIdx.x % nchunk);
+  const int j = chunk * kBlock + (int)threadIdx.x;
+  const bool valid = j < g.nv;
+  const int jj = valid ? j : (int)g.nv - 1;
+  const Vel vel = velocity_of(g, jj);
+  const double wt = valid ? vel.w : 0.0;
+  const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
+  const int S = g.tabw;
+  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
+  const ST* fin = (const ST*)A.fin;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = 0; i < g.ns; ++i) {
+    const int64_t node = e * g.ns + i;
+    const double fv = (double)fin[f_offset(g, e, i, jj)];
+    const double c = wt * collision_term(A.etab + node * S, vel.b[0], oy, oz, S, fv);
+    double m[5] = {c, c * vel.u[0], c * vel.u[1], c * vel.u[2], c * psi4};
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) m[q] += __shfl_xor(m[q], o, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) red[wave][q] = m[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) sum += red[w][threadIdx.x];
+      A.partials[((int64_t)chunk * g.nx + node) * 5 + threadIdx.x] = sum;
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -429,7 +470,7 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
   const int key = A.g.dim * 10 + (A.g.n1 - 1);
   // dynamic LDS: equilibrium rows (relaxation), then, in the 1-D/2-D
   // kernels, the MFMA staging of the moment partials in the same bytes
-  const size_t tab = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(ST) : 0;
+  const size_t tab = A.collide ? (size_t)A.g.ns * A.g.tabw * sizeof(double) : 0;
   const size_t lds = mode != 1 ? std::max(tab, (size_t)mfma_lds_bytes<ST>()) : tab;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
@@ -558,6 +599,21 @@ hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_newton<16>, dim3(grid_of(A.g.nx * 16, 256)), dim3(256), 0, s, A);
   return hipGetLastError();
+}
+
+hipError_t launch_collision_moments(int precision, const StageArgs& A, double* Cm,
+                                    hipStream_t s) {
+  const int nchunk = (int)((A.g.nv + kBlock - 1) / kBlock);
+  const dim3 grid((unsigned)(A.g.ne * nchunk)), block(kBlock);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_collision_moments<double>, grid, block, 0, s, A, nchunk);
+  else
+    hipLaunchKernelGGL(k_collision_moments<float>, grid, block, 0, s, A, nchunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  DevGeom g = A.g;
+  g.nchunk = nchunk;
+  return launch_reduce_partials(g, A.partials, Cm, s);
 }
 
 hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,

@@ -23,6 +23,10 @@ hipError_t launch_newton(const NewtonArgs& A, hipStream_t s);
 hipError_t launch_wall(int precision, const WallArgs& W, hipStream_t s);
 hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,
                                   hipStream_t s);
+// Moments of the collision term of the stage input A.fin into Cm[nx][5]
+// (uses A.partials as scratch).
+hipError_t launch_collision_moments(int precision, const StageArgs& A, double* Cm,
+                                    hipStream_t s);
 hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,
                              hipStream_t s);
 hipError_t launch_to_storage(int precision, const DevGeom& g, const double* in, void* out,

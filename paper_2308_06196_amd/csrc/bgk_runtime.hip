@@ -220,8 +220,8 @@ bgk_status validate(const bgk_problem* pb) {
     for (int k = 0; k < pb->dim; ++k) ns *= pb->order + 1;
     const double nv = (double)pb->nvel[0] * pb->nvel[1] * pb->nvel[2];
     if (nv >= 2147483647.0) return fail(BGK_ERR_UNSUPPORTED, "velocity grid too large");
-    const size_t tab = (size_t)ns * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1) *
-                       (pb->precision == BGK_FP64 ? 8 : 4);
+    // equilibrium rows are FP64 for every storage precision
+    const size_t tab = (size_t)ns * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1) * 8;
     if (tab > (size_t)kMaxTabBytes)
       return fail(BGK_ERR_UNSUPPORTED, "equilibrium factors of one element (%zu B) exceed LDS", tab);
   }
@@ -342,6 +342,21 @@ StageArgs stage_args(const bgk_solver* s) {
     }
     for (int a = 0; a < kMaxN1; ++a) q.w[a] = (float)o.w[a];
     q.Wsum = (float)o.Wsum;
+    // line operators with the inflow-face correction folded in (FP64, then
+    // rounded): Dp = D - G_in lam_own^T, E = G_in lam_ext^T
+    LineOps& lo = A.lops;
+    memset(&lo, 0, sizeof(lo));
+    const int n1 = s->g.n1;
+    for (int pos = 0; pos < 2; ++pos) {
+      const double* lown = pos ? o.lamL : o.lamR;
+      const double* gin = pos ? o.GL : o.GR;
+      for (int i = 0; i < n1; ++i)
+        for (int k = 0; k < n1; ++k) {
+          lo.Dp[pos][i][k] = (float)(o.D[i][k] - gin[i] * lown[k]);
+          for (int ur = 0; ur < 2; ++ur)
+            lo.E[pos][ur][i][k] = (float)(gin[i] * (ur ? o.lamR[k] : o.lamL[k]));
+        }
+    }
   }
   A.params = s->params();
   A.etab = s->etab();
@@ -381,7 +396,6 @@ NewtonArgs newton_args(const bgk_solver* s) {
   N.tol = s->pb.newton_tol > 0.0 ? s->pb.newton_tol : 1e-14;
   N.maxit = s->pb.newton_maxit > 0 ? s->pb.newton_maxit : 20;
   N.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
-  N.etab_f32 = s->precision != BGK_FP64 ? 1 : 0;
   N.continuous = s->pb.equilibrium == BGK_EQ_CONTINUOUS ? 1 : 0;
   return N;
 }
@@ -959,6 +973,37 @@ bgk_status bgk_moments(bgk_solver* s, double* Q, int32_t where) {
   return check_failed(s);
 }
 
+bgk_status bgk_collision_moments(bgk_solver* s, double* Cm, int32_t where) {
+  if (!s || !Cm) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  if (!s->has_state) return fail(BGK_ERR_STATE, "no state installed");
+  if (where != BGK_HOST && where != BGK_DEVICE) return fail(BGK_ERR_INVALID_ARG, "bad where");
+  if (s->failed) return fail(BGK_ERR_STATE, "solver failed earlier; install a new state");
+  if (s->in_batch) return fail(BGK_ERR_STATE, "solver is a batch member");
+  const size_t bytes = (size_t)s->L.nx * 5 * 8;
+  if (!(s->pb.mu_ref > 0.0)) {  // collisions off: the term is zero
+    if (where == BGK_HOST) {
+      memset(Cm, 0, bytes);
+      return BGK_OK;
+    }
+    HIP_TRY(hipMemsetAsync(Cm, 0, bytes, s->stream));
+    return check_failed(s);
+  }
+  bgk_status st = ensure_counters(s);
+  if (st) return st;
+  if ((st = ensure_partials(s))) return st;
+  NewtonArgs N = newton_args(s);
+  N.Q = nullptr;
+  HIP_TRY(launch_newton(N, s->stream));
+  StageArgs A = stage_args(s);
+  A.fin = s->state();
+  double* dst = where == BGK_DEVICE ? Cm : s->Q();
+  HIP_TRY(launch_collision_moments(s->precision, A, dst, s->stream));
+  s->partials_valid = false;  // the partials buffer served as scratch
+  if (where == BGK_HOST)
+    HIP_TRY(hipMemcpyAsync(Cm, s->Q(), bytes, hipMemcpyDeviceToHost, s->stream));
+  return check_failed(s);
+}
+
 bgk_status bgk_stable_dt(bgk_solver* s, double cfl, double* dt) {
   if (!s || !dt) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
   if (!(cfl > 0.0)) return fail(BGK_ERR_INVALID_ARG, "cfl must be > 0");
@@ -1014,6 +1059,7 @@ bgk_status bgk_diagnostics(bgk_solver* s, bgk_diag* out) {
   out->limiter_hits = (int64_t)d[2];
   out->limiter_bad = (int64_t)d[3];
   out->stages = (int64_t)d[4];
+  out->positivity_violations = (int64_t)d[5];
   if (d[1] > 0) {
     s->failed = true;
     return fail(BGK_ERR_NEWTON, "%llu node solve(s) failed", d[1]);

@@ -69,12 +69,13 @@ def integrals(pb: dict, Q: np.ndarray, gamma: float = 5.0 / 3.0) -> dict:
 
 
 def tgv_history(n: int = 16, order: int = 3, nv1: int = 16, steps: int = 100, every: int = 10,
-                precisions=(bgk.FP64, bgk.FP32, bgk.BF16), cfl: float = 0.1) -> list:
+                precisions=(bgk.FP64, bgk.FP32, bgk.BF16), cfl: float = 0.1,
+                dt: float | None = None) -> list:
     """Kinetic energy and enstrophy every `every` steps of the Taylor-Green box in
-    each storage precision (same time step for all)."""
+    each storage precision (same time step for all: dt, or the stable step of the
+    first run's initial state)."""
     pb = wl.tgv3d(n=n, order=order, nv1=nv1)
     rows = []
-    dt = None
     for prec in precisions:
         s = bgk.Solver(pb, precision=prec)
         try:

@@ -107,3 +107,82 @@ def test_request_loop_completes_mix(torch):
     print(m)
     assert m["completed"] == len(reqs) and m["failed"] == 0
     assert m["p99_s"] >= m["p50_s"] > 0
+
+
+def test_batch_admission_mid_run_matches_solo(torch):
+    """Continuous batching: a member admitted after the others have stepped, and a
+    member that completes while the others go on, each end bitwise equal to the
+    same request run alone (members never exchange data; the graph is
+    re-captured around them)."""
+    from paper_2308_06196_amd import bgk
+    _say("batch mid-run admission")
+    stream = torch.cuda.Stream()
+    steps = [9, 3, 6]  # MIX[0] long, MIX[1] finishes early, MIX[3] joins late
+    idx = [0, 1, 3]
+    solo = []
+    for i, n in zip(idx, steps):
+        pb, kind, args, _ = MIX[i]
+        s, dt = _solver(torch, pb, kind, args, stream)
+        s.rk3_step(dt, n)
+        solo.append(s.get_state().cpu().numpy())
+        s.close()
+    batch = bgk.Batch(stream, 4)
+    members = []
+    for i, n in zip(idx[:2], steps[:2]):
+        pb, kind, args, _ = MIX[i]
+        s, dt = _solver(torch, pb, kind, args, stream)
+        batch.add(s, dt, n)
+        members.append(s)
+    got = {}
+    batch.step(2)  # both members have stepped before the third arrives
+    pb, kind, args, _ = MIX[idx[2]]
+    s, dt = _solver(torch, pb, kind, args, stream)
+    batch.add(s, dt, steps[2])
+    members.append(s)
+    for _ in range(30):
+        batch.step(1)
+        for m, err in batch.poll():
+            assert err is None
+            got[members.index(m)] = m.get_state().cpu().numpy()
+        if batch.size() == 0:
+            break
+    assert len(got) == 3
+    for k in range(3):
+        assert np.array_equal(got[k], solo[k]), k
+    batch.close()
+
+
+def test_batch_many_recaptures_between_polls(torch):
+    """More than 16 membership changes without a poll: replaced graphs pile up
+    until the batch synchronises its stream and releases them (the bound on
+    graphs held between polls); every member still ends bitwise equal to its
+    solo run."""
+    from paper_2308_06196_amd import bgk
+    _say("batch recapture churn")
+    stream = torch.cuda.Stream()
+    pb_long, kind_long, args_long, _ = MIX[1]
+    pb_short, kind_short, args_short, _ = MIX[0]
+    s, dt_long = _solver(torch, pb_long, kind_long, args_long, stream)
+    s.rk3_step(dt_long, 24)
+    ref_long = s.get_state().cpu().numpy()
+    s.close()
+    s, dt_short = _solver(torch, pb_short, kind_short, args_short, stream)
+    s.rk3_step(dt_short, 1)
+    ref_short = s.get_state().cpu().numpy()
+    s.close()
+    batch = bgk.Batch(stream, 32)
+    long_m, _ = _solver(torch, pb_long, kind_long, args_long, stream)
+    batch.add(long_m, dt_long, 24)
+    shorts = []
+    for _ in range(20):  # every cycle: one admission and one completion
+        m, _ = _solver(torch, pb_short, kind_short, args_short, stream)
+        batch.add(m, dt_short, 1)
+        shorts.append(m)
+        batch.step(1)
+    batch.step(10)
+    done = dict((id(m), err) for m, err in batch.poll())
+    assert len(done) == 21 and all(e is None for e in done.values())
+    assert np.array_equal(long_m.get_state().cpu().numpy(), ref_long)
+    for m in shorts:
+        assert np.array_equal(m.get_state().cpu().numpy(), ref_short)
+    batch.close()
