@@ -46,15 +46,20 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+# host-side runtime sources: they do not change what a stage kernel reads or writes
+HOST_SOURCES = ("bgk_runtime.hip", "bgk_launch.hpp")
+
+
 def kernel_source_hash(csrc: str | None = None) -> str:
-    """Hash of the HIP sources with comments and whitespace removed, so that the
+    """Hash of the kernel sources (device code and launch configuration; the
+    host runtime excluded) with comments and whitespace removed, so that the
     stored HBM traffic (profiles/traffic.json) is used only for the kernels it
     was measured on."""
     import re
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_2308_06196_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".hpp")):
+        if fn.endswith((".hip", ".hpp")) and fn not in HOST_SOURCES:
             src = open(os.path.join(csrc, fn)).read()
             src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
             src = re.sub(r"//[^\n]*", " ", src)
