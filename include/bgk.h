@@ -250,6 +250,32 @@ bgk_status bgk_moments(bgk_solver* s, double* Q, int32_t where);
  * partials of the state. */
 bgk_status bgk_collision_moments(bgk_solver* s, double* Cm, int32_t where);
 
+/* Maximum scratch of bgk_residual_noalloc: a static device array of this many
+ * bytes per GPU the library runs on, held until the process ends. */
+#define BGK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * residual r = L(f) of bgk_residual for problem *pb without a solver or
+ * workspace. f_in and r_out are device buffers in the canonical FP64 layout
+ * (nx*nv doubles each, caller-owned); everything else the kernels use (the
+ * internal copy of f in the storage precision, moment partials, equilibrium
+ * parameters and rows, counters) lives in the library's static scratch array
+ * of BGK_NOALLOC_SCRATCH_BYTES bytes. Calls no hipMalloc, hipFree or memset:
+ * kernels only, queued on hip_stream (a hipStream_t or NULL), asynchronous;
+ * the counters are cleared by a kernel at the start of every call. The
+ * result equals bgk_residual's for the same problem and input.
+ * Errors: BGK_ERR_INVALID_ARG / BGK_ERR_UNSUPPORTED as bgk_query_footprint;
+ * BGK_ERR_UNSUPPORTED for diffuse walls; BGK_ERR_OUT_OF_MEMORY (nothing
+ * queued) when the problem needs more scratch than the array holds (about
+ * 2.5M phase-space DOF in FP64 storage). Numerical failures are not reported
+ * (nothing synchronises): r_out then holds NaN where an equilibrium solve
+ * failed. Every call on one GPU shares that GPU's scratch array: calls that
+ * overlap in time on one GPU (different streams, or threads) race; calls on
+ * one stream are ordered. */
+bgk_status bgk_residual_noalloc(const bgk_problem* pb, const double* f_in, double* r_out,
+                                void* hip_stream);
+
 /* Time step dt = min(cfl / max_j sum_{k<d} |u_jk| / h_k, min_nodes tau) of
  * the installed state. Synchronises. */
 bgk_status bgk_stable_dt(bgk_solver* s, double cfl, double* dt);

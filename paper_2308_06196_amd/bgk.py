@@ -128,6 +128,7 @@ def lib():
             "bgk_rk3_step": [vp, C.c_double, i32],
             "bgk_moments": [vp, vp, i32],
             "bgk_collision_moments": [vp, vp, i32],
+            "bgk_residual_noalloc": [pp, vp, vp, vp],
             "bgk_stable_dt": [vp, C.c_double, dp],
             "bgk_diagnostics": [vp, C.POINTER(Diag)],
             "bgk_synchronize": [vp],
@@ -165,6 +166,26 @@ def footprint(pb: dict, precision: int = FP64):
     b, nx, nv = C.c_size_t(0), C.c_int64(0), C.c_int64(0)
     _check(lib().bgk_query_footprint(C.byref(s), C.byref(b), C.byref(nx), C.byref(nv)))
     return int(b.value), int(nx.value), int(nv.value)
+
+
+def residual_noalloc(pb: dict, f_in, out=None, precision: int = FP64, stream=None):
+    """Residual L(f) of problem pb for a device tensor f_in (canonical FP64
+    layout) without a solver or workspace: the library keeps its scratch in a
+    static device array (bgk_residual_noalloc). out: a float64 device tensor of
+    the same size, or None for a new one (allocated here by torch, outside the
+    library call). Queued on `stream` (default: torch's current stream)."""
+    import torch
+    assert isinstance(f_in, torch.Tensor) and f_in.is_cuda and f_in.dtype == torch.float64
+    assert f_in.is_contiguous()
+    if out is None:
+        out = torch.empty_like(f_in)
+    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+    assert out.numel() == f_in.numel()
+    st = problem_struct(pb, precision)
+    stream = stream if stream is not None else torch.cuda.current_stream(f_in.device)
+    _check(lib().bgk_residual_noalloc(C.byref(st), C.c_void_p(f_in.data_ptr()),
+                                      C.c_void_p(out.data_ptr()), C.c_void_p(stream.cuda_stream)))
+    return out
 
 
 class Solver:

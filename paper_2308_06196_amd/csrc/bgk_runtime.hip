@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -600,6 +601,52 @@ bgk_status reset_state_flags(bgk_solver* s) {
 
 }  // namespace
 
+namespace {
+
+// Fill a solver object for problem *pb over the device memory ws (a validated
+// problem). With brick = false the elements are visited in lexicographic
+// order (results are the same bit for bit; the brick order only improves
+// cache reuse of hexahedral neighbours) and, without diffuse walls, the
+// host side allocates nothing.
+void init_solver(bgk_solver* s, const bgk_problem* pb, char* ws, hipStream_t stream, bool brick) {
+  s->pb = *pb;
+  s->L = layout_of(pb);
+  s->ws = ws;
+  s->stream = stream;
+  s->precision = pb->precision;
+  s->gamma = pb->gamma > 0.0 ? pb->gamma : 5.0 / 3.0;
+  DevGeom& g = s->g;
+  memset(&g, 0, sizeof(g));
+  g.dim = pb->dim;
+  g.n1 = pb->order + 1;
+  g.ns = s->L.ns;
+  for (int k = 0; k < 3; ++k) {
+    g.nelem[k] = k < pb->dim ? pb->nelem[k] : 1;
+    g.bc[k][0] = k < pb->dim ? pb->bc[k][0] : 0;
+    g.bc[k][1] = k < pb->dim ? pb->bc[k][1] : 0;
+    g.scale[k] = k < pb->dim ? 2.0 / ((pb->xhi[k] - pb->xlo[k]) / pb->nelem[k]) : 0.0;
+    g.nv1[k] = pb->nvel[k];
+    g.vlo[k] = pb->vlo[k];
+    g.du[k] = (pb->vhi[k] - pb->vlo[k]) / (pb->nvel[k] - 1);
+  }
+  g.tabw = pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1;
+  g.ne = s->L.ne;
+  g.nx = s->L.nx;
+  g.nv = s->L.nv;
+  g.nvb = s->L.nvb;
+  g.nchunk = s->L.nchunk;
+  // velocity slots: octants of the signs of the transported components. FP64
+  // hexahedra keep the lexicographic order (no split): their plane-split
+  // kernels measured 4 % faster with it on the 16^3 x 16^3 Taylor-Green box,
+  // where the FP32 hexahedra ran 6 % faster with the octants.
+  set_velocity_slots(g, !(pb->dim == 3 && pb->precision == BGK_FP64));
+  build_ops(g.n1, g.dim, s->op);
+  if (brick && pb->dim == 3) brick_order(g.nelem, s->order_host);
+  setup_walls(s);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bgk_status_str(bgk_status st) {
@@ -645,40 +692,7 @@ bgk_status bgk_create(const bgk_problem* pb, void* ws, size_t bytes, void* strea
     return fail(BGK_ERR_OUT_OF_MEMORY, "workspace %zu bytes < footprint %zu", bytes, need);
   bgk_solver* s = new (std::nothrow) bgk_solver();
   if (!s) return fail(BGK_ERR_OUT_OF_MEMORY, "host allocation failed");
-  s->pb = *pb;
-  s->L = layout_of(pb);
-  s->ws = (char*)ws;
-  s->stream = (hipStream_t)stream;
-  s->precision = pb->precision;
-  s->gamma = pb->gamma > 0.0 ? pb->gamma : 5.0 / 3.0;
-  DevGeom& g = s->g;
-  memset(&g, 0, sizeof(g));
-  g.dim = pb->dim;
-  g.n1 = pb->order + 1;
-  g.ns = s->L.ns;
-  for (int k = 0; k < 3; ++k) {
-    g.nelem[k] = k < pb->dim ? pb->nelem[k] : 1;
-    g.bc[k][0] = k < pb->dim ? pb->bc[k][0] : 0;
-    g.bc[k][1] = k < pb->dim ? pb->bc[k][1] : 0;
-    g.scale[k] = k < pb->dim ? 2.0 / ((pb->xhi[k] - pb->xlo[k]) / pb->nelem[k]) : 0.0;
-    g.nv1[k] = pb->nvel[k];
-    g.vlo[k] = pb->vlo[k];
-    g.du[k] = (pb->vhi[k] - pb->vlo[k]) / (pb->nvel[k] - 1);
-  }
-  g.tabw = pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1;
-  g.ne = s->L.ne;
-  g.nx = s->L.nx;
-  g.nv = s->L.nv;
-  g.nvb = s->L.nvb;
-  g.nchunk = s->L.nchunk;
-  // velocity slots: octants of the signs of the transported components. FP64
-  // hexahedra keep the lexicographic order (no split): their plane-split
-  // kernels measured 4 % faster with it on the 16^3 x 16^3 Taylor-Green box,
-  // where the FP32 hexahedra ran 6 % faster with the octants.
-  set_velocity_slots(g, !(pb->dim == 3 && pb->precision == BGK_FP64));
-  build_ops(g.n1, g.dim, s->op);
-  if (pb->dim == 3) brick_order(g.nelem, s->order_host);
-  setup_walls(s);
+  init_solver(s, pb, (char*)ws, (hipStream_t)stream, true);
   *out = s;
   return BGK_OK;
 }
@@ -1070,6 +1084,108 @@ bgk_status bgk_diagnostics(bgk_solver* s, bgk_diag* out) {
 bgk_status bgk_synchronize(bgk_solver* s) {
   if (!s) return fail(BGK_ERR_INVALID_ARG, "NULL solver");
   return check_failed(s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Residual without allocation: the solver's device memory is a file-scope
+// device array (one copy per GPU the library runs on, held until the process
+// ends). Host code reaches that memory only through the address
+// hipGetSymbolAddress returns for the current device; the array's name in
+// host code is not a device address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[BGK_NOALLOC_SCRATCH_BYTES];
+
+// Set n 64-bit words to a value (a kernel, where a memset node is not wanted:
+// the entry point below may sit under graph capture).
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int64_t n,
+                                                   unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the scratch array on the current device, looked up once per device.
+bgk_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(BGK_ERR_UNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(BGK_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BGK_OK;
+}
+
+// Residual layout inside the scratch array: one internal copy of the input,
+// then the partials, equilibrium parameters and rows, and the counters (the
+// solver's other regions are not used by a residual evaluation).
+Layout residual_layout(const bgk_problem* pb) {
+  Layout L = layout_of(pb);
+  size_t off = 0;
+  L.f[0] = L.f[1] = L.f[2] = 0;
+  off = align_up(L.fbytes);
+  L.partials = off;
+  off = align_up(off + (size_t)L.nx * L.nchunk * 5 * sizeof(double));
+  L.params = off;
+  off = align_up(off + (size_t)L.nx * 8 * sizeof(double));
+  L.etab = off;
+  off = align_up(off + (size_t)L.nx * (pb->nvel[0] + pb->nvel[1] + pb->nvel[2] + 1) *
+                           sizeof(double));
+  L.diag = off;
+  off = align_up(off + 8 * sizeof(unsigned long long));
+  L.order = L.Q = L.prim = L.wallp = L.wall_part = L.wall_rho = off;
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+bgk_status bgk_residual_noalloc(const bgk_problem* pb, const double* f_in, double* r_out,
+                                void* hip_stream) {
+  if (!pb || !f_in || !r_out) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  bgk_status st = bgk_query_footprint(pb, nullptr, nullptr, nullptr);
+  if (st) return st;
+  for (int k = 0; k < pb->dim; ++k)
+    if (pb->bc[k][0] == BGK_BC_DIFFUSE || pb->bc[k][1] == BGK_BC_DIFFUSE)
+      return fail(BGK_ERR_UNSUPPORTED, "bgk_residual_noalloc: diffuse walls are not supported");
+  const Layout L = residual_layout(pb);
+  if (L.total > (size_t)BGK_NOALLOC_SCRATCH_BYTES)
+    return fail(BGK_ERR_OUT_OF_MEMORY,
+                "bgk_residual_noalloc: problem needs %zu bytes of scratch, the static array holds %zu",
+                L.total, (size_t)BGK_NOALLOC_SCRATCH_BYTES);
+  void* base = nullptr;
+  if ((st = scratch_address(&base))) return st;
+  // solver object on the stack: lexicographic element order, no diffuse walls,
+  // so nothing is allocated on the host either
+  bgk_solver s;
+  init_solver(&s, pb, (char*)base, (hipStream_t)hip_stream, false);
+  s.L = L;
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, s.stream, s.diag(), (int64_t)8, 0ull);
+  HIP_TRY(hipGetLastError());
+  const int64_t n = L.nx * L.nv;
+  HIP_TRY(launch_to_storage(s.precision, s.g, f_in, s.f(0), 0, n, s.stream));
+  if ((st = moments_of(&s, s.f(0)))) return st;
+  NewtonArgs N = newton_args(&s);
+  N.Q = nullptr;
+  HIP_TRY(launch_newton(N, s.stream));
+  StageArgs A = stage_args(&s);
+  A.fin = s.f(0);
+  A.out = r_out;
+  HIP_TRY(launch_stage(s.precision, 1, A, s.stream));
+  return BGK_OK;
 }
 
 }  // extern "C"
