@@ -9,7 +9,12 @@ in FP64 and with FP32 bulk storage / FP64 collision side by side.
 Prints one JSON line: value = FP64 DOF-updates/s; "mixed" holds the FP32-bulk
 path, "mixed_bf16" the path with an FP32 state and BF16 stage increments;
 "roofline" the dominant kernel (fused stage) against HBM peak;
-"cpu_baseline" the FP64 oracle timed on a bounded sample on the host.
+"collision_conservation" the largest relative discrete moment of the collision
+term of each path's final state; "workloads" the 3-D Taylor-Green box (FP32,
+BF16 increments, FP64) and the Mach-2 box (FP32), each with its roofline entry;
+"serving" the request mix (batched server against the plain FP64 path);
+"cpu_baseline" the FP64 oracle timed on a bounded sample on the host's cores
+(all of them and one).
 """
 from __future__ import annotations
 
@@ -51,13 +56,19 @@ HOST_SOURCES = ("bgk_runtime.hip", "bgk_launch.hpp")
 
 
 def kernel_source_hash(csrc: str | None = None) -> str:
-    """Hash of the kernel sources (device code and launch configuration; the
-    host runtime excluded) with comments and whitespace removed, so that the
+    """Hash of the compile flags and the kernel sources (device code and launch
+    configuration; the host runtime excluded) with comments and whitespace
+    removed, so that the
     stored HBM traffic (profiles/traffic.json) is used only for the kernels it
     was measured on."""
     import re
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_2308_06196_amd", "csrc")
+    # compile flags that shape the device code (include paths left out)
+    from paper_2308_06196_amd import build as _build
+    fl = _build.FLAGS
+    h.update(" ".join(f for i, f in enumerate(fl)
+                      if f != "-I" and not (i and fl[i - 1] == "-I")).encode() + b"\0")
     for fn in sorted(os.listdir(csrc)):
         if fn.endswith((".hip", ".hpp")) and fn not in HOST_SOURCES:
             src = open(os.path.join(csrc, fn)).read()
@@ -71,7 +82,22 @@ DTYPE = {0: "f64", 1: "f32-bulk/f64-collision",
          2: "f32-state/bf16-stage-increments/f64-collision"}
 
 
-def run_gpu(pb, prim_fn, precision, steps, warmup):
+def collision_conservation(s, pb):
+    """Largest relative discrete moment of the collision term of the solver's
+    state (bgk_collision_moments), scaled per node by (rho, rho, rho, rho, E)/tau."""
+    import numpy as np
+    Q = s.moments().cpu().numpy()
+    Cm = s.collision_moments().cpu().numpy()
+    gamma = pb["gamma"] or 5.0 / 3.0
+    rho, E = Q[:, 0], Q[:, 4]
+    P = (gamma - 1.0) * (E - 0.5 * (Q[:, 1:4] ** 2).sum(1) / rho)
+    th = P / rho
+    mu = pb["mu_ref"] * (th / pb["theta_ref"]) ** pb["omega"]
+    scale = np.column_stack([rho] * 4 + [E]) * (P / mu)[:, None]
+    return float((np.abs(Cm) / scale).max())
+
+
+def run_gpu(pb, prim_fn, precision, steps, warmup, conservation=False):
     import torch
 
     from paper_2308_06196_amd import bgk
@@ -90,10 +116,11 @@ def run_gpu(pb, prim_fn, precision, steps, warmup):
     tm = s.timing_read()
     s.timing(False)
     diag = s.diagnostics()
+    cons = collision_conservation(s, pb) if conservation else None
     dof = s.nx * s.nv
     out = {"dof": dof, "elapsed_s": el, "ms_per_step": 1e3 * el / steps,
            "value": dof * steps / el, "timing": tm, "diag": diag, "dt": dt,
-           "precision": precision,
+           "precision": precision, "collision_conservation": cons,
            # compulsory bytes per DOF per stage launch, averaged over the three
            # stages: 8s/3 for a stored state of s bytes (read input, [read f^n],
            # write output); BF16 increments: (4+2, 4+2+2, 4+2+4) B = 8 B
@@ -165,14 +192,36 @@ def cpu_baseline(pb_full, prim_fn, budget_s=12.0):
                       f"direct velocity sums"}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_in_process(workload_name, threads, budget_s):
+    """cpu_baseline in a child process with OMP_NUM_THREADS = threads (the
+    oracle's OpenMP team size is fixed when its library loads)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                          "--workload", workload_name, "--cpu-budget", str(budget_s)],
+                         env=env, capture_output=True, text=True, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
 def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
             kinds=("sod1d", "box2d"), policy="sjf"):
     """Serving mix (shock tubes and periodic boxes, p in 1..3, 8^3..32^3 velocities,
     Kn log-uniform [1e-4, 1], 100 steps each). A saturating run (all requests at
     t = 0) measures the capacity; then the same requests arrive as a Poisson
     stream at 0.8 x that rate. The comparator is the plain FP64 path: the same
-    kernels, one request at a time, no overlap, on the same two arrival
-    patterns (latency from the resulting queue)."""
+    kernels launched directly, one request at a time in arrival order, no
+    overlap, on the same two arrival patterns, timed on the wall clock with the
+    same set-up work per request (solver, initial state, time step)."""
     from paper_2308_06196_amd import serve
     from paper_2308_06196_amd import workloads as wl
     pool = int(pool_gb * (1 << 30))
@@ -188,11 +237,19 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
         ex.close()
         return m
 
+    def say(what, m):
+        print(f"[bench] serving {what}: {m['completed']} of {m['requests']} completed in "
+              f"{m['span_s']:.2f} s, p50 {m['p50_s']:.3f} s", file=sys.stderr, flush=True)
+
     sat = batched(None)
+    say("batched, all at t = 0", sat)
     cap_rate = sat["completed"] / sat["span_s"]
     pois = batched(0.8 * cap_rate)
-    seq_sat = serve.run_sequential(reqs(None))
-    seq_pois = serve.run_sequential(reqs(0.8 * cap_rate))
+    say("batched, Poisson", pois)
+    seq_sat = serve.run_sequential(reqs(None), pool)
+    say("sequential FP64, all at t = 0", seq_sat)
+    seq_pois = serve.run_sequential(reqs(0.8 * cap_rate), pool)
+    say("sequential FP64, Poisson", seq_pois)
     return {"requests": n_requests, "steps_each": steps, "kinds": list(kinds),
             "policy": policy, "max_members": max_members,
             "total_dof": int(sum(r.dof for r in reqs(None))),
@@ -211,7 +268,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="precision of the headline value")
-    ap.add_argument("--serving", type=int, default=24, metavar="N",
+    ap.add_argument("--serving", type=int, default=256, metavar="N",
                     help="requests in the serving mix (0: skip)")
     ap.add_argument("--serving-steps", type=int, default=100)
     ap.add_argument("--serving-policy", default="sjf", choices=["fifo", "sjf"],
@@ -220,6 +277,11 @@ def main():
                     help="requests resident in the batch at once")
     ap.add_argument("--serving-kinds", default="sod1d,box2d",
                     help="request kinds of the serving mix (sod1d, box2d, channel2d)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the Taylor-Green and Mach-2 lines")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only time the CPU oracle on the workload's sample and print it")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "calibrates the HBM byte counters against a known traffic")
@@ -233,13 +295,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}))
         return
+    if a.cpu_baseline_only:
+        pb, prim_fn, _ = workload(a.workload)
+        print(json.dumps(cpu_baseline(pb, prim_fn, a.cpu_budget)), flush=True)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note only)"}))
         sys.exit(2)
     pb, prim_fn, desc = workload(a.workload)
     main_prec = {"fp64": 0, "fp32": 1, "bf16": 2}[a.precision]
-    res = run_gpu(pb, prim_fn, main_prec, a.steps, a.warmup)
+    res = run_gpu(pb, prim_fn, main_prec, a.steps, a.warmup, conservation=True)
     print(f"[bench] {a.workload} {a.precision}: {res['value']:.4e} DOF-updates/s, "
           f"{res['ms_per_step']:.3f} ms/step, timing {res['timing']}", file=sys.stderr, flush=True)
     line = {
@@ -252,17 +318,35 @@ def main():
                    "limiter_hits": res["diag"]["limiter_hits"]},
         "roofline": roofline(res, a.steps, a.workload),
     }
+    cons = {DTYPE[main_prec]: res["collision_conservation"]}
     if not a.no_mixed and main_prec == 0:
-        mx = run_gpu(pb, prim_fn, 1, a.steps, a.warmup)
-        print(f"[bench] {a.workload} fp32-bulk: {mx['value']:.4e} DOF-updates/s, "
-              f"{mx['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-        line["mixed"] = {"dtype": DTYPE[1], "value": mx["value"],
-                         "ms_per_step": mx["ms_per_step"], "roofline": roofline(mx, a.steps, a.workload)}
-        bf = run_gpu(pb, prim_fn, 2, a.steps, a.warmup)
-        print(f"[bench] {a.workload} bf16-increments: {bf['value']:.4e} DOF-updates/s, "
-              f"{bf['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-        line["mixed_bf16"] = {"dtype": DTYPE[2], "value": bf["value"],
-                              "ms_per_step": bf["ms_per_step"], "roofline": roofline(bf, a.steps, a.workload)}
+        for key, prec, label in (("mixed", 1, "fp32-bulk"), ("mixed_bf16", 2, "bf16-increments")):
+            mx = run_gpu(pb, prim_fn, prec, a.steps, a.warmup, conservation=True)
+            print(f"[bench] {a.workload} {label}: {mx['value']:.4e} DOF-updates/s, "
+                  f"{mx['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+            line[key] = {"dtype": DTYPE[prec], "value": mx["value"],
+                         "ms_per_step": mx["ms_per_step"],
+                         "roofline": roofline(mx, a.steps, a.workload)}
+            cons[DTYPE[prec]] = mx["collision_conservation"]
+    # discrete moments of the collision term of the final state, relative
+    # (the benchmark spec target 1e-13), per storage precision
+    line["collision_conservation"] = cons
+    if not a.no_workloads and a.workload == "box2d":
+        # the 3-D Taylor-Green box (FP32, BF16 increments, FP64) and the Mach-2 box
+        # (FP32), each with the roofline entry of its stage kernel
+        line["workloads"] = {}
+        for name, prec, steps in (("tgv3d", 1, 5), ("tgv3d", 2, 5), ("tgv3d", 0, 3),
+                                  ("mach2", 1, 3)):
+            wpb, wprim, wdesc = workload(name)
+            r = run_gpu(wpb, wprim, prec, steps, 1)
+            key = f"{name}_{['fp64', 'fp32', 'bf16'][prec]}"
+            line["workloads"][key] = {
+                "workload": wdesc, "dtype": DTYPE[prec], "dof": r["dof"], "steps": steps,
+                "value": r["value"], "unit": "DOF-updates/s", "ms_per_step": r["ms_per_step"],
+                "roofline": roofline(r, steps, name)}
+            print(f"[bench] {key}: {r['value']:.4e} DOF-updates/s, {r['ms_per_step']:.3f} ms/step, "
+                  f"stage frac {line['workloads'][key]['roofline']['frac']}",
+                  file=sys.stderr, flush=True)
     if a.serving:
         sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")),
                      policy=a.serving_policy, max_members=a.serving_members)
@@ -274,7 +358,12 @@ def main():
               f"{sv['sequential_fp64_saturating']['dof_updates_per_s']:.3e} DOF-updates/s",
               file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(pb, prim_fn)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cb = cpu_baseline_in_process(a.workload, threads, a.cpu_budget)
+        one = cpu_baseline_in_process(a.workload, 1, a.cpu_budget)
+        cb["cpu_model"] = cpu_model()
+        cb["single_core"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
+        line["cpu_baseline"] = cb
         print(f"[bench] cpu baseline {line['cpu_baseline']}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 

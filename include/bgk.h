@@ -297,31 +297,49 @@ bgk_status bgk_timing_read(bgk_solver* s, bgk_timing* out);
 bgk_status bgk_synchronize(bgk_solver* s);
 
 /* ------------------------------------------------------------------------
- * Batches (serving): resident solvers advanced together. A replay is one
- * launch of a captured HIP graph in which every member's kernels (the same
- * kernels as bgk_rk3_step) form an independent branch: the member that
- * moves the most bytes per step takes one RK3 step per replay, a member
- * moving W times fewer takes the largest power of two <= W steps (at most
- * its remaining ones), so small requests are not paced by the largest.
- * Members never exchange data, so each member's result is bitwise the one
- * it gets alone. Membership changes (add, completion, remove) re-capture the
- * graph before the next replay. A batch does not own its members: the caller
- * keeps every solver and its workspace alive until the solver has been
- * polled or removed, then may destroy it.
+ * Batches (serving): resident FP64- or FP32-storage solvers of 1-D and 2-D
+ * problems (the SSP-RK3 steps of Sec. 2.2, the same kernels' arithmetic as
+ * bgk_rk3_step) advanced together. The arguments of every member live in
+ * descriptor tables in a caller-supplied device workspace. A replay runs up
+ * to four sub-steps, each three RK stages of [the equilibrium solves of the
+ * members per team size, the diffuse-wall densities, one stage launch per
+ * kernel family (dimension, order, storage precision)], each launch covering
+ * all members of its kind with one work-group per work unit. The member that
+ * moves the most bytes per step takes one step per replay, a member moving W
+ * times fewer takes the largest power of two <= min(W, 4) (at most its
+ * remaining steps), so small requests are not paced by the largest. Members
+ * never exchange data and every work unit runs the same arithmetic as in
+ * bgk_rk3_step, so each member's result is bitwise the one it gets alone.
+ * Admission, completion and removal rewrite the tables (copied on the batch
+ * stream from pinned host staging, ahead of the launches that read them). A
+ * batch does not own its members: the caller keeps every solver and its
+ * workspace alive until the solver has been polled or removed, then may
+ * destroy it.
  * ------------------------------------------------------------------------ */
 typedef struct bgk_batch bgk_batch;
 
-/* Create a batch on hip_stream (NULL = default stream) with room for
- * max_members (1..4096) concurrent members. Host-only allocation. */
-bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, bgk_batch** out);
+/* Bytes of device workspace a batch of max_members (1..64) members needs
+ * (descriptor tables; independent of the members' sizes). */
+bgk_status bgk_batch_query_footprint(int32_t max_members, size_t* bytes);
 
-/* Add solver s (state installed, created on the batch's stream, timing off,
- * not in another batch) to advance nsteps >= 1 steps of size dt.
- * BGK_ERR_OUT_OF_MEMORY when the batch is full. */
+/* Create a batch on hip_stream (NULL = default stream) with room for
+ * max_members (1..64) concurrent members. d_workspace: device memory of at
+ * least bgk_batch_query_footprint(max_members) bytes, 256-byte aligned, owned
+ * by the caller and kept until bgk_batch_destroy returns. Allocates two
+ * pinned host staging buffers of the same size (released by destroy).
+ * BGK_ERR_OUT_OF_MEMORY if bytes is too small. */
+bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, void* d_workspace, size_t bytes,
+                            bgk_batch** out);
+
+/* Add solver s (state installed, FP64 or FP32 storage, 1-D or 2-D problem,
+ * created on the batch's stream, timing off, not in another batch) to advance
+ * nsteps >= 1 steps of size dt. BGK_ERR_OUT_OF_MEMORY when the batch is full;
+ * BGK_ERR_UNSUPPORTED for BF16 increments or hexahedra (step those with
+ * bgk_rk3_step). */
 bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps);
 
-/* Queue nsteps graph replays (see above; a member stops after its own step
- * count and becomes pollable). Asynchronous on the batch stream. */
+/* Queue nsteps replays (see above; a member stops after its own step count
+ * and becomes pollable). Asynchronous on the batch stream. */
 bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps);
 
 /* Synchronise with the batch stream and hand back up to cap members that
@@ -337,7 +355,8 @@ bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s);
 /* Number of active members (0 for NULL). */
 int32_t bgk_batch_size(const bgk_batch* b);
 
-/* Wait for queued work and release the batch (members are not touched). */
+/* Wait for queued work and release the batch (members and workspace are not
+ * touched). */
 bgk_status bgk_batch_destroy(bgk_batch* b);
 
 const char* bgk_status_str(bgk_status st);

@@ -135,7 +135,8 @@ def lib():
             "bgk_timing_enable": [vp, i32],
             "bgk_timing_read": [vp, C.POINTER(Timing)],
             "bgk_set_stream": [vp, vp],
-            "bgk_batch_create": [vp, i32, C.POINTER(vp)],
+            "bgk_batch_query_footprint": [i32, C.POINTER(C.c_size_t)],
+            "bgk_batch_create": [vp, i32, vp, C.c_size_t, C.POINTER(vp)],
             "bgk_batch_add": [vp, vp, C.c_double, C.c_int64],
             "bgk_batch_step": [vp, i32],
             "bgk_batch_poll": [vp, C.POINTER(vp), C.POINTER(i32), i32, C.POINTER(i32)],
@@ -339,15 +340,23 @@ class Solver:
 
 
 class Batch:
-    """Resident solvers advanced together by graph replay (libbgk batch C-ABI).
-    Members must be created on the batch's stream."""
+    """Resident solvers advanced together by launches over descriptor tables
+    (libbgk batch C-ABI): one launch per kernel family covers all its members. Members must be created on the batch's stream;
+    FP64 or FP32 storage, 1-D or 2-D problems. The tables live in a torch
+    device buffer owned by this object."""
 
     def __init__(self, stream, max_members: int = 64):
+        import torch
         self.stream = stream
         self.max_members = max_members
+        nbytes = C.c_size_t(0)
+        _check(lib().bgk_batch_query_footprint(int(max_members), C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=stream.device)
+        base = self.workspace.data_ptr()
+        ptr = (base + 255) // 256 * 256
         self._b = C.c_void_p()
         _check(lib().bgk_batch_create(C.c_void_p(stream.cuda_stream), int(max_members),
-                                      C.byref(self._b)))
+                                      C.c_void_p(ptr), nbytes.value, C.byref(self._b)))
         self._members = {}
 
     def add(self, solver: Solver, dt: float, nsteps: int):
@@ -379,8 +388,9 @@ class Batch:
 
     def close(self):
         if self._b:
-            lib().bgk_batch_destroy(self._b)
+            lib().bgk_batch_destroy(self._b)  # waits for the batch stream
             self._b = C.c_void_p()
+            self.workspace = None
 
     def __del__(self):
         try:

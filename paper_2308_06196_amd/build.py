@@ -1,7 +1,11 @@
 """Build libbgk.so (HIP for gfx950) in-tree with hipcc.
 
 Every HIP translation unit is compiled with packed-FP32 instructions turned
-off. The library lands next to this file and is what the binding loads.
+off, and with floating-point contraction limited to single source expressions
+(-ffp-contract=on): which multiply-adds fuse is then fixed by the source, so
+code that is inlined into several kernels (one stage work item in the
+single-solver and the batched stage kernels) rounds identically in each. The
+library lands next to this file and is what the binding loads.
 """
 from __future__ import annotations
 
@@ -18,7 +22,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["bgk_runtime.hip", "bgk_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 

@@ -653,10 +653,11 @@ constexpr int stage_waves() {
 // (line_mfma), with the relaxation term formed in FP64 and added to the FP32
 // stage combination in FP64 before the stored value is rounded.
 // ---------------------------------------------------------------------------
+// Work item w (element x velocity chunk, velocity-chunk major) of one stage
+// launch; k_stage runs one item per work-group, k_stage_batch several members'
+// items from a descriptor table.
 template <int DIM, int P, typename ST, int MODE, bool INC = false>
-__global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
-    k_stage(const StageArgs A) {
+__device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) {
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
   using CT = typename Compute<ST>::T;
   // FR line contractions on the matrix cores for FP32 arithmetic on p = 3
@@ -682,7 +683,6 @@ __global__ void __launch_bounds__(kBlock)
   face_rows_store<CT, N1>(fr, OP);
   LineOps& lo = lops[kMfma ? threadIdx.x >> 6 : 0];
   if constexpr (kMfma) line_ops_store(lo, A.lops);
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = (int)(w / A.ecount);
   const int64_t e = work_element(A.order, A.e0, w, A.ecount);
   const int64_t nv = g.nv;
@@ -992,7 +992,7 @@ __global__ void __launch_bounds__(kBlock)
   }
 
   if constexpr (MODE == 1) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
+    if (threadIdx.x == 0 && w == 0) atomicAdd(&A.diag[4], 1ull);
   } else {
     if (A.limiter) {
       CT fmin = o[0];
@@ -1052,8 +1052,79 @@ __global__ void __launch_bounds__(kBlock)
     // with them
     if (A.collide) lds_barrier();
     element_partials_mfma<NS, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, dyn_lds, red);
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
+    if (threadIdx.x == 0 && w == 0) atomicAdd(&A.diag[4], 1ull);
   }
+}
+
+template <int DIM, int P, typename ST, int MODE, bool INC = false>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
+    k_stage(const StageArgs A) {
+  stage_item<DIM, P, ST, MODE, INC>(A, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// Descriptor tables of a batch (serving): the arguments of every member slot
+// live in device memory (StageArgs for each of the three RK stages, the
+// NewtonArgs, the WallArgs for each stage), and one BatchList per launch names
+// the members it covers and the prefix sums of their work units, so that one
+// launch covers every member of a kernel family and a change of membership
+// rewrites tables instead of rebuilding launch arguments.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatchMembers = 64;
+
+// Pointer into a descriptor table. The tables are rewritten by copies between
+// launches and never during one, so kernels read them through the constant
+// address space: uniform loads from it become scalar loads that the compiler
+// may repeat where a value is used, instead of vector loads whose results
+// would stay live in vector registers across the work loop.
+template <typename T>
+using table_ptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ const T& table_entry(table_ptr<T> p, int64_t i) {
+  return *(const T*)&p[i];
+}
+struct BatchList {
+  int32_t n;     // members covered
+  int32_t pad;
+  int32_t slot[kMaxBatchMembers];              // member slots
+  // prefix sums of the members' work units (the host keeps every total
+  // below 2^31): stage work items (element x chunk), equilibrium
+  // work-groups of 256 lanes, wall-flux work-groups, wall-density
+  // work-groups of 256 lanes
+  int32_t stage_off[kMaxBatchMembers + 1];
+  int32_t newton_off[kMaxBatchMembers + 1];
+  int32_t wflux_off[kMaxBatchMembers + 1];
+  int32_t wrho_off[kMaxBatchMembers + 1];
+};
+
+// Member of the list whose range of work units holds unit t (off[m] <= t <
+// off[m + 1]), by bisection; uniform over a work-group. Members with no
+// units share their offset with the next member, and the largest such m is
+// the one whose range is not empty.
+__device__ __forceinline__ int batch_member(const __attribute__((address_space(4))) int32_t* off,
+                                           int n, int32_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Stage launch over the members of one kernel family (dimension, order,
+// storage precision) at RK stage `stage`: one work-group per item of every
+// member in the list (the host sizes the grid to the list's item count), the
+// items dealt to the XCDs in contiguous ranges as in k_stage.
+template <int DIM, int P, typename ST, int MODE>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, false>())))
+    k_stage_batch(table_ptr<StageArgs> args, table_ptr<BatchList> list, int stage) {
+  // one item per work-group; the grid is the list's item count
+  const int32_t u = (int32_t)xcd_remap(blockIdx.x, gridDim.x);
+  const int m = batch_member(list->stage_off, list->n, u);
+  stage_item<DIM, P, ST, MODE>(table_entry(args, list->slot[m] * 3 + stage),
+                               u - list->stage_off[m]);
 }
 
 // Moment partials of a stored state (first stage after installation).

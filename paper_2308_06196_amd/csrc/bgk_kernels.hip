@@ -79,9 +79,8 @@ __device__ __forceinline__ double team_sum(double x) {
 // meshes use 2- or 4-lane teams (less redundant solve work), small ones
 // 16-lane teams (enough waves to fill the device).
 template <int kTeam>
-__global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
+__device__ __forceinline__ void newton_item(const NewtonArgs& A, const int64_t node_raw) {
   const DevGeom& g = A.g;
-  const int64_t node_raw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kTeam;
   const int r = threadIdx.x % kTeam;
   // teams past the last node work on the last node and store nothing, so that
   // every lane reaches the wave-level counter reduction at the end
@@ -274,6 +273,23 @@ __global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
   }
 }
 
+template <int kTeam>
+__global__ void __launch_bounds__(256) k_newton(const NewtonArgs A) {
+  newton_item<kTeam>(A, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kTeam);
+}
+
+// Equilibrium solves of the batch members of one team size: whole work-groups
+// of 256 lanes per member, so that a work-group's arguments are uniform; the
+// grid is the list's work-group count.
+template <int kTeam>
+__global__ void __launch_bounds__(256) k_newton_batch(table_ptr<NewtonArgs> args,
+                                                      table_ptr<BatchList> list) {
+  const int32_t t = blockIdx.x;
+  const int m = batch_member(list->newton_off, list->n, t);
+  newton_item<kTeam>(table_entry(args, list->slot[m]),
+                     ((int64_t)(t - list->newton_off[m]) * 256 + threadIdx.x) / kTeam);
+}
+
 // Q[node][5] from the partials (no Newton solve).
 __global__ void __launch_bounds__(256) k_reduce_partials(const DevGeom g, const double* partials,
                                                          double* Q) {
@@ -345,12 +361,11 @@ __global__ void __launch_bounds__(kBlock) k_collision_moments(const StageArgs A,
 // flux points' partial sums are reduced in a fixed order (lanes by an xor
 // butterfly, then the four waves in LDS).
 template <int DIM, int P, typename ST>
-__global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
+__device__ __forceinline__ void wall_flux_item(const WallArgs& W, const int b) {
   constexpr int N1 = P + 1;
   constexpr int NF = ipow(N1, DIM - 1);
   __shared__ double red[kBlock / 64][NF];
   const DevGeom& g = W.g;
-  const int b = blockIdx.x;
   int q = 0;
   while (q + 1 < W.nside && b >= W.blk0[q + 1]) ++q;
   const int k = W.side_k[q], side = W.side_s[q];
@@ -400,10 +415,23 @@ __global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
   }
 }
 
+template <int DIM, int P, typename ST>
+__global__ void __launch_bounds__(kBlock) k_wall_flux(const WallArgs W) {
+  wall_flux_item<DIM, P, ST>(W, blockIdx.x);
+}
+
+template <int DIM, int P, typename ST>
+__global__ void __launch_bounds__(kBlock) k_wall_flux_batch(table_ptr<WallArgs> args,
+                                                            table_ptr<BatchList> list, int stage) {
+  const int32_t t = blockIdx.x;  // grid: the list's wall-flux work-groups
+  const int m = batch_member(list->wflux_off, list->n, t);
+  wall_flux_item<DIM, P, ST>(table_entry(args, list->slot[m] * 3 + stage),
+                             (int)(t - list->wflux_off[m]));
+}
+
 // rho_w per wall flux point: the chunk partials summed in order, times the
 // inverse incoming flux of the side's unit wall Maxwellian.
-__global__ void __launch_bounds__(256) k_wall_rho(const WallArgs W) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void wall_rho_item(const WallArgs& W, const int t) {
   if (t >= W.npoints) return;
   int q = 0;
   while (q + 1 < W.nside && t >= W.off[q + 1]) ++q;
@@ -411,6 +439,18 @@ __global__ void __launch_bounds__(256) k_wall_rho(const WallArgs W) {
   double sum = 0.0;
   for (int c = 0; c < W.g.nchunk; ++c) sum += p[c];
   W.rho[t] = sum * W.wallp[(W.side_k[q] * 2 + W.side_s[q]) * 8 + 5];
+}
+
+__global__ void __launch_bounds__(256) k_wall_rho(const WallArgs W) {
+  wall_rho_item(W, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_wall_rho_batch(table_ptr<WallArgs> args,
+                                                        table_ptr<BatchList> list, int stage) {
+  const int32_t t = blockIdx.x;  // grid: the list's wall-density work-groups
+  const int m = batch_member(list->wrho_off, list->n, t);
+  wall_rho_item(table_entry(args, list->slot[m] * 3 + stage),
+                (int)((t - list->wrho_off[m]) * 256 + threadIdx.x));
 }
 
 // Continuous Maxwellian sampled at every (node, velocity); one work-group =
@@ -592,9 +632,10 @@ hipError_t launch_newton(const NewtonArgs& A, hipStream_t s) {
   // (measured on 16,384 nodes: 0.045 ms against 0.076 ms with 16 lanes and
   // 0.047 ms with 2), of 2 lanes on large meshes (262,144 nodes: 0.146 ms
   // against 0.240 ms with 4; 884,736 nodes: 0.54 ms against 0.72 ms)
-  if (A.g.nx >= 131072)
+  const int team = newton_team(A.g.nx);
+  if (team == 2)
     hipLaunchKernelGGL(k_newton<2>, dim3(grid_of(A.g.nx * 2, 256)), dim3(256), 0, s, A);
-  else if (A.g.nx >= 8192)
+  else if (team == 4)
     hipLaunchKernelGGL(k_newton<4>, dim3(grid_of(A.g.nx * 4, 256)), dim3(256), 0, s, A);
   else
     hipLaunchKernelGGL(k_newton<16>, dim3(grid_of(A.g.nx * 16, 256)), dim3(256), 0, s, A);
@@ -615,6 +656,88 @@ hipError_t launch_collision_moments(int precision, const StageArgs& A, double* C
   g.nchunk = nchunk;
   return launch_reduce_partials(g, A.partials, Cm, s);
 }
+
+hipError_t launch_stage_batch(int precision, int dim, int order, int stage, const StageArgs* args,
+                              const BatchList* list, size_t tab_bytes, unsigned grid,
+                              hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  const size_t lds = std::max(tab_bytes, (size_t)(precision == 0 ? mfma_lds_bytes<double>()
+                                                                  : mfma_lds_bytes<float>()));
+#define BGK_BATCH(D, P)                                                                       \
+  case D * 10 + P:                                                                          \
+    if (precision == 0) {                                                                   \
+      if (stage == 0)                                                                       \
+        hipLaunchKernelGGL((k_stage_batch<D, P, double, 3>), dim3(grid), dim3(kBlock), lds, s, \
+                           (table_ptr<StageArgs>)args, (table_ptr<BatchList>)list, stage);                                              \
+      else                                                                                  \
+        hipLaunchKernelGGL((k_stage_batch<D, P, double, 0>), dim3(grid), dim3(kBlock), lds, s, \
+                           (table_ptr<StageArgs>)args, (table_ptr<BatchList>)list, stage);                                              \
+    } else {                                                                                \
+      if (stage == 0)                                                                       \
+        hipLaunchKernelGGL((k_stage_batch<D, P, float, 3>), dim3(grid), dim3(kBlock), lds, s, \
+                           (table_ptr<StageArgs>)args, (table_ptr<BatchList>)list, stage);                                              \
+      else                                                                                  \
+        hipLaunchKernelGGL((k_stage_batch<D, P, float, 0>), dim3(grid), dim3(kBlock), lds, s, \
+                           (table_ptr<StageArgs>)args, (table_ptr<BatchList>)list, stage);                                              \
+    }                                                                                       \
+    break;
+  switch (dim * 10 + order) {
+    BGK_BATCH(1, 1) BGK_BATCH(1, 2) BGK_BATCH(1, 3)
+    BGK_BATCH(2, 1) BGK_BATCH(2, 2) BGK_BATCH(2, 3)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef BGK_BATCH
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_batch(int team, const NewtonArgs* args, const BatchList* list,
+                               unsigned grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  if (team == 16)
+    hipLaunchKernelGGL(k_newton_batch<16>, dim3(grid), dim3(256), 0, s, (table_ptr<NewtonArgs>)args,
+                       (table_ptr<BatchList>)list);
+  else if (team == 4)
+    hipLaunchKernelGGL(k_newton_batch<4>, dim3(grid), dim3(256), 0, s, (table_ptr<NewtonArgs>)args,
+                       (table_ptr<BatchList>)list);
+  else
+    hipLaunchKernelGGL(k_newton_batch<2>, dim3(grid), dim3(256), 0, s, (table_ptr<NewtonArgs>)args,
+                       (table_ptr<BatchList>)list);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_flux_batch(int precision, int dim, int order, int stage,
+                                  const WallArgs* args, const BatchList* list, unsigned grid,
+                                  hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+#define BGK_WBATCH(D, P)                                                                        \
+  case D * 10 + P:                                                                            \
+    if (precision == 0)                                                                       \
+      hipLaunchKernelGGL((k_wall_flux_batch<D, P, double>), dim3(grid), dim3(kBlock), 0, s, \
+                         (table_ptr<WallArgs>)args, (table_ptr<BatchList>)list, stage);                                                        \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_wall_flux_batch<D, P, float>), dim3(grid), dim3(kBlock), 0, s, \
+                         (table_ptr<WallArgs>)args, (table_ptr<BatchList>)list, stage);                                                        \
+    break;
+  switch (dim * 10 + order) {
+    BGK_WBATCH(1, 1) BGK_WBATCH(1, 2) BGK_WBATCH(1, 3)
+    BGK_WBATCH(2, 1) BGK_WBATCH(2, 2) BGK_WBATCH(2, 3)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef BGK_WBATCH
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_rho_batch(int stage, const WallArgs* args, const BatchList* list,
+                                 unsigned grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wall_rho_batch, dim3(grid), dim3(256), 0, s, (table_ptr<WallArgs>)args,
+                     (table_ptr<BatchList>)list, stage);
+  return hipGetLastError();
+}
+
+int newton_team(int64_t nx) { return nx >= 131072 ? 2 : nx >= 8192 ? 4 : 16; }
 
 hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, double* Q,
                                   hipStream_t s) {

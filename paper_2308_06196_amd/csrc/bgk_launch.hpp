@@ -27,6 +27,23 @@ hipError_t launch_reduce_partials(const DevGeom& g, const double* partials, doub
 // (uses A.partials as scratch).
 hipError_t launch_collision_moments(int precision, const StageArgs& A, double* Cm,
                                     hipStream_t s);
+// Team size of the equilibrium solve for a mesh of nx nodes.
+int newton_team(int64_t nx);
+// Batched launches over descriptor tables in device memory (1-D and 2-D
+// members, FP64 or FP32 storage): RK stage `stage` of the members of one
+// kernel family, the equilibrium solves of the members of one team size, the
+// diffuse-wall fluxes of one family and the wall densities of all members.
+// grid: the list's work units (one per work-group); 0 launches nothing.
+hipError_t launch_stage_batch(int precision, int dim, int order, int stage, const StageArgs* args,
+                              const BatchList* list, size_t tab_bytes, unsigned grid,
+                              hipStream_t s);
+hipError_t launch_newton_batch(int team, const NewtonArgs* args, const BatchList* list,
+                               unsigned grid, hipStream_t s);
+hipError_t launch_wall_flux_batch(int precision, int dim, int order, int stage,
+                                  const WallArgs* args, const BatchList* list, unsigned grid,
+                                  hipStream_t s);
+hipError_t launch_wall_rho_batch(int stage, const WallArgs* args, const BatchList* list,
+                                 unsigned grid, hipStream_t s);
 hipError_t launch_maxwellian(int precision, const DevGeom& g, const double* prim, void* f,
                              hipStream_t s);
 hipError_t launch_to_storage(int precision, const DevGeom& g, const double* in, void* out,

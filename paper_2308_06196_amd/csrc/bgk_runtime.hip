@@ -1191,123 +1191,256 @@ bgk_status bgk_residual_noalloc(const bgk_problem* pb, const double* f_in, doubl
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Batches: resident solvers advanced together by replaying one captured
-// graph, in which every member's kernels (a few RK3 steps each) form an
-// independent branch (fork/join events on the batch stream). A change of
-// membership re-captures the graph before the next replay.
+// Batches: resident solvers advanced together. The arguments of every member
+// live in descriptor tables in the batch's device workspace: the StageArgs of
+// its three RK stages, its NewtonArgs and the WallArgs of its stages, and per
+// launch a BatchList naming the members it covers with the prefix sums of
+// their work units. A replay runs up to kSub sub-steps; each is three RK
+// stages of [equilibrium solves per team size, wall fluxes per family and wall
+// densities, one stage launch per kernel family (dimension, order, storage
+// precision)], every launch covering all members of its list, with the grid
+// set to the list's work units. Admission and completion rewrite the tables
+// (copied on the batch stream, ahead of the launches that read them).
 // ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kSub = 4;            // sub-steps per replay (a member takes up to 4 steps)
+constexpr int kMaxFamilies = 12;   // dimension 1-2 x order 1-3 x FP64/FP32
+constexpr int kTeamLists = 3;      // equilibrium teams of 16, 4, 2 lanes
+constexpr int kAllList = kMaxFamilies + kTeamLists;  // every member (wall densities)
+constexpr int kListsPerSub = kAllList + 1;
+constexpr int kTeamOfList[kTeamLists] = {16, 4, 2};
+
+struct TableLayout {
+  size_t args, nargs, wargs, lists, total;
+};
+
+TableLayout table_layout() {
+  TableLayout t;
+  size_t off = 0;
+  t.args = off;
+  off = align_up(off + sizeof(StageArgs) * kMaxBatchMembers * 3);
+  t.nargs = off;
+  off = align_up(off + sizeof(NewtonArgs) * kMaxBatchMembers);
+  t.wargs = off;
+  off = align_up(off + sizeof(WallArgs) * kMaxBatchMembers * 3);
+  t.lists = off;
+  off = align_up(off + sizeof(BatchList) * kSub * kListsPerSub);
+  t.total = off;
+  return t;
+}
+
+int team_index(int team) { return team == 16 ? 0 : team == 4 ? 1 : 2; }
+
+// work units of a member: stage work items, equilibrium work-groups
+int64_t member_units(const bgk_solver* s) { return s->L.ne * s->L.nchunk; }
+int64_t member_newton_blocks(const bgk_solver* s) {
+  return (s->L.nx * newton_team(s->L.nx) + 255) / 256;
+}
+
+}  // namespace
+
 struct bgk_batch {
   hipStream_t stream;
   int32_t max_members;
+  char* ws;
+  TableLayout tl;
   struct Member {
     bgk_solver* s;
     double dt;
     int64_t remaining;
-    int64_t per_replay;  // steps per graph replay (set at capture)
+    int64_t per_replay;  // steps per replay (set when the tables are written)
+    int slot;
+    int family;
+  };
+  struct Family {
+    int dim, order, precision;
+    size_t tab_bytes;  // dynamic LDS of its stage launches (equilibrium rows)
   };
   std::vector<Member> members;
   std::vector<bgk_solver*> finished;  // stepped to completion, not yet polled
-  std::vector<hipStream_t> branches;
-  std::vector<hipEvent_t> joins;
-  hipEvent_t fork = nullptr;
-  hipGraphExec_t exec = nullptr;
-  // replaced graphs whose last replay may still be executing; destroyed at
-  // the next point where the batch stream has been synchronized
-  std::vector<hipGraphExec_t> retired;
-  bool dirty = true;
+  std::vector<int> free_slots;
+  std::vector<Family> fams;           // families the lists can name
+  bool tables_dirty = true;
+  // work units of every list as last written: [sub][list] stage, newton,
+  // wall-flux, wall-density (the launch grids)
+  int32_t units[kSub][kListsPerSub][4];
+  // pinned host staging of the tables, two buffers used in turn; an event
+  // marks when the copy out of each has executed
+  char* host[2] = {nullptr, nullptr};
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  bool copy_pending[2] = {false, false};
+  int next_host = 0;
+  StageArgs* d_args() const { return (StageArgs*)(ws + tl.args); }
+  NewtonArgs* d_nargs() const { return (NewtonArgs*)(ws + tl.nargs); }
+  WallArgs* d_wargs() const { return (WallArgs*)(ws + tl.wargs); }
+  BatchList* d_list(int sub, int l) const {
+    return (BatchList*)(ws + tl.lists) + sub * kListsPerSub + l;
+  }
 };
 
 namespace {
 
-// Destroy the replaced graphs; the batch stream must have been synchronized.
-void release_retired(bgk_batch* b) {
-  for (hipGraphExec_t g : b->retired) (void)hipGraphExecDestroy(g);
-  b->retired.clear();
-}
-
-bgk_status batch_capture(bgk_batch* b) {
-  if (b->exec) {
-    // its last replay may still be running: destroying it now would free
-    // what the device and the runtime still use
-    b->retired.push_back(b->exec);
-    b->exec = nullptr;
-    if (b->retired.size() > 16) {  // bound what is held between polls
-      HIP_TRY(hipStreamSynchronize(b->stream));
-      release_retired(b);
-    }
-  }
-  const size_t n = b->members.size();
-  while (b->branches.size() < n) {
-    hipStream_t st;
-    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    b->branches.push_back(st);
-    hipEvent_t ev;
-    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    b->joins.push_back(ev);
-  }
-  if (n == 0) {
-    b->dirty = false;
-    return BGK_OK;
-  }
-  // Work balance: the member moving the most bytes per step takes one step
-  // per replay; a member moving W times fewer takes the largest power of two
-  // <= W (at most its remaining steps), so small requests are not paced by
-  // the largest one.
+// Steps per replay: the member moving the most bytes per step takes one; a
+// member moving W times fewer takes the largest power of two <= W (at most
+// kSub and its remaining steps), so small requests are not paced by the
+// largest.
+void balance(bgk_batch* b) {
   double wmax = 0.0;
   for (auto& m : b->members) wmax = std::max(wmax, (double)m.s->L.fbytes);
   for (auto& m : b->members) {
     const double ratio = wmax / std::max(1.0, (double)m.s->L.fbytes);
     int64_t k = 1;
-    while (2.0 * k <= ratio && 2 * k <= m.remaining && k < 1024) k *= 2;
+    while (2.0 * k <= ratio && 2 * k <= kSub) k *= 2;
     m.per_replay = std::min<int64_t>(k, m.remaining);
   }
-  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  bgk_status rc = BGK_OK;
-  hipError_t e = hipEventRecord(b->fork, b->stream);
-  for (size_t i = 0; i < n && e == hipSuccess && rc == BGK_OK; ++i) {
-    e = hipStreamWaitEvent(b->branches[i], b->fork, 0);
-    if (e != hipSuccess) break;
-    rc = rk3_launch(b->members[i].s, b->members[i].dt, (int32_t)b->members[i].per_replay,
-                    b->branches[i], false);
-    if (rc) break;
-    e = hipEventRecord(b->joins[i], b->branches[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->joins[i], 0);
+}
+
+// Write every descriptor into the next host staging buffer and queue its copy
+// to the device tables on the batch stream.
+bgk_status upload_tables(bgk_batch* b) {
+  balance(b);
+  const int h = b->next_host;
+  b->next_host ^= 1;
+  if (b->copy_pending[h]) HIP_TRY(hipEventSynchronize(b->copied[h]));
+  char* host = b->host[h];
+  StageArgs* args = (StageArgs*)(host + b->tl.args);
+  NewtonArgs* nargs = (NewtonArgs*)(host + b->tl.nargs);
+  WallArgs* wargs = (WallArgs*)(host + b->tl.wargs);
+  BatchList* lists = (BatchList*)(host + b->tl.lists);
+  static const double kA[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double kB[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (auto& m : b->members) {
+    bgk_solver* s = m.s;
+    // the arguments bgk_rk3_step passes for FP64/FP32 storage
+    StageArgs A = stage_args(s);
+    A.dt = m.dt;
+    A.fn = s->f(0);
+    for (int k = 0; k < 3; ++k) {
+      A.fin = s->f(k);
+      A.out = s->f((k + 1) % 3);
+      A.a = kA[k];
+      A.b = kB[k];
+      args[m.slot * 3 + k] = A;
+      WallArgs W = s->wall;
+      W.fin = s->f(k);
+      wargs[m.slot * 3 + k] = W;
+    }
+    NewtonArgs N = newton_args(s);
+    N.Q = nullptr;
+    nargs[m.slot] = N;
   }
-  hipGraph_t graph = nullptr;
-  hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
-  if (rc) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc;
+  for (int sub = 0; sub < kSub; ++sub) {
+    BatchList* L = lists + sub * kListsPerSub;
+    for (int l = 0; l < kListsPerSub; ++l) {
+      L[l].n = 0;
+      L[l].stage_off[0] = L[l].newton_off[0] = L[l].wflux_off[0] = L[l].wrho_off[0] = 0;
+    }
+    for (auto& m : b->members) {
+      if (m.per_replay <= sub) continue;
+      const bgk_solver* s = m.s;
+      const int64_t wf = s->wall.nside ? s->wall.blk0[s->wall.nside] : 0;
+      const int64_t wr = s->wall.nside ? (s->wall.npoints + 255) / 256 : 0;
+      const int ls[3] = {m.family, kMaxFamilies + team_index(newton_team(s->L.nx)), kAllList};
+      for (int l : ls) {
+        BatchList& B = L[l];
+        const int i = B.n++;
+        B.slot[i] = m.slot;
+        B.stage_off[i + 1] = B.stage_off[i] + (int32_t)(l == m.family ? member_units(s) : 0);
+        B.newton_off[i + 1] = B.newton_off[i] + (int32_t)member_newton_blocks(s);
+        B.wflux_off[i + 1] = B.wflux_off[i] + (int32_t)wf;
+        B.wrho_off[i + 1] = B.wrho_off[i] + (int32_t)wr;
+      }
+    }
+    for (int l = 0; l < kListsPerSub; ++l) {
+      const BatchList& B = L[l];
+      b->units[sub][l][0] = B.stage_off[B.n];
+      b->units[sub][l][1] = B.newton_off[B.n];
+      b->units[sub][l][2] = B.wflux_off[B.n];
+      b->units[sub][l][3] = B.wrho_off[B.n];
+    }
   }
-  if (e != hipSuccess || e2 != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return fail(BGK_ERR_DEVICE, "graph capture: %s",
-                hipGetErrorString(e != hipSuccess ? e : e2));
-  }
-  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return fail(BGK_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-  b->dirty = false;
+  HIP_TRY(hipMemcpyAsync(b->ws, host, b->tl.total, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipEventRecord(b->copied[h], b->stream));
+  b->copy_pending[h] = true;
+  b->tables_dirty = false;
   return BGK_OK;
+}
+
+// One replay: the launches of every sub-step whose lists are not empty.
+bgk_status replay(bgk_batch* b) {
+  hipError_t e = hipSuccess;
+  for (int sub = 0; sub < kSub && e == hipSuccess; ++sub) {
+    if (b->units[sub][kAllList][1] == 0) break;  // no member takes this sub-step
+    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
+      for (int t = 0; t < kTeamLists && e == hipSuccess; ++t)
+        e = launch_newton_batch(kTeamOfList[t], b->d_nargs(), b->d_list(sub, kMaxFamilies + t),
+                                (unsigned)b->units[sub][kMaxFamilies + t][1], b->stream);
+      for (size_t f = 0; f < b->fams.size() && e == hipSuccess; ++f)
+        e = launch_wall_flux_batch(b->fams[f].precision, b->fams[f].dim, b->fams[f].order, stage,
+                                   b->d_wargs(), b->d_list(sub, (int)f),
+                                   (unsigned)b->units[sub][f][2], b->stream);
+      if (e == hipSuccess)
+        e = launch_wall_rho_batch(stage, b->d_wargs(), b->d_list(sub, kAllList),
+                                  (unsigned)b->units[sub][kAllList][3], b->stream);
+      for (size_t f = 0; f < b->fams.size() && e == hipSuccess; ++f)
+        e = launch_stage_batch(b->fams[f].precision, b->fams[f].dim, b->fams[f].order, stage,
+                               b->d_args(), b->d_list(sub, (int)f), b->fams[f].tab_bytes,
+                               (unsigned)b->units[sub][f][0], b->stream);
+    }
+  }
+  if (e != hipSuccess) return fail(BGK_ERR_DEVICE, "batch launch: %s", hipGetErrorString(e));
+  return BGK_OK;
+}
+
+void destroy_batch_host(bgk_batch* b) {
+  for (int h = 0; h < 2; ++h) {
+    if (b->host[h]) (void)hipHostFree(b->host[h]);
+    if (b->copied[h]) (void)hipEventDestroy(b->copied[h]);
+  }
 }
 
 }  // namespace
 
 extern "C" {
 
-bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, bgk_batch** out) {
+bgk_status bgk_batch_query_footprint(int32_t max_members, size_t* bytes) {
+  if (!bytes) return fail(BGK_ERR_INVALID_ARG, "bytes is NULL");
+  if (max_members < 1 || max_members > kMaxBatchMembers)
+    return fail(BGK_ERR_INVALID_ARG, "max_members must be in 1..%d", kMaxBatchMembers);
+  *bytes = table_layout().total;
+  return BGK_OK;
+}
+
+bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, void* d_workspace, size_t bytes,
+                            bgk_batch** out) {
   if (!out) return fail(BGK_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (max_members < 1 || max_members > 4096)
-    return fail(BGK_ERR_INVALID_ARG, "max_members must be in 1..4096");
+  size_t need = 0;
+  bgk_status st = bgk_batch_query_footprint(max_members, &need);
+  if (st) return st;
+  if (!d_workspace) return fail(BGK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)d_workspace) % kAlign)
+    return fail(BGK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (bytes < need)
+    return fail(BGK_ERR_OUT_OF_MEMORY, "batch workspace %zu bytes < footprint %zu", bytes, need);
   bgk_batch* b = new (std::nothrow) bgk_batch();
   if (!b) return fail(BGK_ERR_OUT_OF_MEMORY, "host allocation failed");
   b->stream = (hipStream_t)hip_stream;
   b->max_members = max_members;
-  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    delete b;
-    return fail(BGK_ERR_DEVICE, "event: %s", hipGetErrorString(e));
+  b->ws = (char*)d_workspace;
+  b->tl = table_layout();
+  memset(b->units, 0, sizeof(b->units));
+  for (int i = max_members - 1; i >= 0; --i) b->free_slots.push_back(i);
+  for (int h = 0; h < 2; ++h) {
+    hipError_t e = hipHostMalloc((void**)&b->host[h], b->tl.total, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied[h], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      destroy_batch_host(b);
+      delete b;
+      return fail(BGK_ERR_DEVICE, "batch staging: %s", hipGetErrorString(e));
+    }
+    memset(b->host[h], 0, b->tl.total);
   }
   *out = b;
   return BGK_OK;
@@ -1317,7 +1450,7 @@ bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps)
   if (!b || !s) return fail(BGK_ERR_INVALID_ARG, "NULL argument");
   if (!(dt > 0.0) || !isfinite(dt)) return fail(BGK_ERR_INVALID_ARG, "dt must be > 0");
   if (nsteps < 1) return fail(BGK_ERR_INVALID_ARG, "nsteps < 1");
-  if ((int32_t)b->members.size() >= b->max_members)
+  if (b->free_slots.empty())
     return fail(BGK_ERR_OUT_OF_MEMORY, "batch is full (%d members)", b->max_members);
   if (s->stream != b->stream) return fail(BGK_ERR_INVALID_ARG, "solver and batch streams differ");
   if (s->in_batch) return fail(BGK_ERR_STATE, "solver already in a batch");
@@ -1327,11 +1460,40 @@ bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps)
   if (s->precision == BGK_BF16)
     return fail(BGK_ERR_UNSUPPORTED, "BF16 storage alternates its state buffer between steps; "
                 "step it with bgk_rk3_step");
+  if (s->pb.dim > 2)
+    return fail(BGK_ERR_UNSUPPORTED, "batches hold 1-D and 2-D problems; step hexahedral "
+                "problems with bgk_rk3_step");
+  {
+    // the work-unit prefix sums of a launch are 32-bit
+    int64_t units = member_units(s), nb = member_newton_blocks(s);
+    for (auto& m : b->members) {
+      units += member_units(m.s);
+      nb += member_newton_blocks(m.s);
+    }
+    if (units > INT32_MAX || nb > INT32_MAX)
+      return fail(BGK_ERR_UNSUPPORTED, "batch work would exceed 2^31 work-groups per launch; "
+                  "step this solver with bgk_rk3_step");
+  }
   bgk_status st = ensure_partials(s);
   if (st) return st;
+  // family of the member's stage kernels
+  int fam = -1;
+  for (size_t f = 0; f < b->fams.size(); ++f)
+    if (b->fams[f].dim == s->pb.dim && b->fams[f].order == s->pb.order &&
+        b->fams[f].precision == s->precision)
+      fam = (int)f;
+  const size_t tab = s->pb.mu_ref > 0.0 ? (size_t)s->L.ns * s->g.tabw * sizeof(double) : 0;
+  if (fam < 0) {
+    if ((int)b->fams.size() >= kMaxFamilies) return fail(BGK_ERR_UNSUPPORTED, "too many families");
+    b->fams.push_back({s->pb.dim, s->pb.order, s->precision, tab});
+    fam = (int)b->fams.size() - 1;
+  }
+  b->fams[fam].tab_bytes = std::max(b->fams[fam].tab_bytes, tab);
+  const int slot = b->free_slots.back();
+  b->free_slots.pop_back();
   s->in_batch = true;
-  b->members.push_back({s, dt, nsteps, 1});
-  b->dirty = true;
+  b->members.push_back({s, dt, nsteps, 1, slot, fam});
+  b->tables_dirty = true;
   return BGK_OK;
 }
 
@@ -1339,20 +1501,22 @@ bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps) {
   if (!b) return fail(BGK_ERR_INVALID_ARG, "NULL batch");
   if (nsteps < 0) return fail(BGK_ERR_INVALID_ARG, "nsteps < 0");
   for (int32_t k = 0; k < nsteps && !b->members.empty(); ++k) {
-    if (b->dirty) {
-      bgk_status st = batch_capture(b);
+    if (b->tables_dirty) {
+      bgk_status st = upload_tables(b);
       if (st) return st;
     }
-    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    bgk_status st = replay(b);
+    if (st) return st;
     size_t w = 0;
     for (size_t i = 0; i < b->members.size(); ++i) {
       bgk_batch::Member& m = b->members[i];
       m.remaining -= m.per_replay;
       if (m.remaining == 0) {
         b->finished.push_back(m.s);
-        b->dirty = true;
+        b->free_slots.push_back(m.slot);
+        b->tables_dirty = true;
       } else {
-        if (m.per_replay > m.remaining) b->dirty = true;  // re-balance near the end
+        if (m.per_replay > m.remaining) b->tables_dirty = true;  // re-balance near the end
         b->members[w++] = m;
       }
     }
@@ -1368,7 +1532,6 @@ bgk_status bgk_batch_poll(bgk_batch* b, bgk_solver** done, int32_t* status, int3
   *ndone = 0;
   if (b->finished.empty()) return BGK_OK;
   HIP_TRY(hipStreamSynchronize(b->stream));
-  release_retired(b);
   int32_t n = 0;
   size_t i = 0;
   for (; i < b->finished.size() && n < cap; ++i) {
@@ -1388,10 +1551,10 @@ bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s) {
   for (size_t i = 0; i < b->members.size(); ++i) {
     if (b->members[i].s == s) {
       HIP_TRY(hipStreamSynchronize(b->stream));
-      release_retired(b);
       s->in_batch = false;
+      b->free_slots.push_back(b->members[i].slot);
       b->members.erase(b->members.begin() + i);
-      b->dirty = true;
+      b->tables_dirty = true;
       return BGK_OK;
     }
   }
@@ -1403,13 +1566,9 @@ int32_t bgk_batch_size(const bgk_batch* b) { return b ? (int32_t)b->members.size
 bgk_status bgk_batch_destroy(bgk_batch* b) {
   if (!b) return BGK_OK;
   (void)hipStreamSynchronize(b->stream);
-  release_retired(b);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
   for (auto& m : b->members) m.s->in_batch = false;
   for (auto* s : b->finished) s->in_batch = false;
-  for (hipStream_t st : b->branches) (void)hipStreamDestroy(st);
-  for (hipEvent_t ev : b->joins) (void)hipEventDestroy(ev);
-  if (b->fork) (void)hipEventDestroy(b->fork);
+  destroy_batch_host(b);
   delete b;
   return BGK_OK;
 }

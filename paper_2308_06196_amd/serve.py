@@ -3,9 +3,9 @@
 Requests (shock tubes, periodic boxes, channels) arrive over time. The server
 admits them (oldest first, or least work first) as soon as their device-memory
 footprint fits the pool and a member slot is free; admitted requests stay resident and advance
-together: each quantum replays one captured graph per RK3 step in which every
-member's kernels form an independent branch, so their work overlaps on the
-device. Finished requests free their memory and slot for waiting ones.
+together: every launch of a quantum covers all members of one kernel family
+(descriptor tables in device memory), so small members' work fills the device
+beside the large ones'. Finished requests free their memory and slot for waiting ones.
 Latency = completion - arrival; p50/p99 and aggregate DOF-updates/s are
 reported.
 
@@ -167,8 +167,8 @@ def make_requests(descs, precision: int = 0) -> List[Request]:
 
 class BatchExecutor(Executor):
     """GPU executor over the libbgk batch C-ABI. Each member owns a torch
-    workspace; all members run on the batch's stream (captured graph with one
-    branch per member)."""
+    workspace; all members run on the batch's stream, each launch covering
+    every member of one kernel family."""
 
     def __init__(self, device="cuda:0", max_members: int = 64, cfl: float = 0.1):
         import torch
@@ -215,30 +215,71 @@ class BatchExecutor(Executor):
         self.batch.close()
 
 
-def run_sequential(requests: List[Request], device="cuda:0", cfl: float = 0.1) -> dict:
-    """The plain path for comparison: one request at a time, FP64 kernels, no
-    overlap; latency measured as if all requests were queued at their arrival
-    time behind the previous ones."""
-    import torch
+class SequentialExecutor(Executor):
+    """The plain path: one request at a time on one stream, its kernels
+    launched by bgk_rk3_step for that request alone (no overlap), with the same
+    set-up work per request as BatchExecutor (solver creation, Maxwellian
+    initial state, stable time step). Driven by a Server with one member slot
+    and first-come-first-served admission, so its latencies are wall-clock
+    times like the batched server's."""
 
-    from . import bgk
-    from . import workloads as wl
-    t0 = time.perf_counter()
-    clock = 0.0
-    for r in sorted(requests, key=lambda r: (r.arrival, r.id)):
-        start = max(clock, r.arrival)
-        s = bgk.Solver(r.problem, precision=r.precision, device=device)
-        s.set_maxwellian(wl.PRIM[r.kind](s.node_coords(), **r.prim_args))
-        dt = s.stable_dt(cfl)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        s.rk3_step(dt, r.steps)
-        s.synchronize()
-        el = time.perf_counter() - a
+    def __init__(self, device="cuda:0", cfl: float = 0.1):
+        import torch
+
+        from . import bgk
+        from . import workloads as wl
+        self.torch, self.bgk, self.wl = torch, bgk, wl
+        self.device = device
+        self.cfl = cfl
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.members = {}  # handle -> [solver, dt, remaining steps]
+
+    def footprint(self, req: Request) -> int:
+        return self.bgk.footprint(req.problem, req.precision)[0]
+
+    def admit(self, req: Request):
+        s = self.bgk.Solver(req.problem, precision=req.precision, device=self.device,
+                            stream=self.stream)
+        s.set_maxwellian(self.wl.PRIM[req.kind](s.node_coords(), **req.prim_args))
+        dt = s.stable_dt(self.cfl)
+        self.members[id(s)] = [s, dt, req.steps]
+        return id(s)
+
+    def step(self, n: int) -> None:
+        for m in self.members.values():
+            k = min(n, m[2])
+            if k:
+                m[0].rk3_step(m[1], k)
+                m[2] -= k
+
+    def poll(self) -> list:
+        out = []
+        for h, (s, _, left) in self.members.items():
+            if left == 0:
+                try:
+                    s.synchronize()
+                    out.append((h, None))
+                except self.bgk.BGKError as exc:
+                    out.append((h, self.bgk.STATUS.get(exc.status, str(exc))))
+        return out
+
+    def release(self, handle) -> None:
+        s = self.members.pop(handle)[0]
         s.close()
-        r.admitted = start
-        clock = start + el
-        r.done = clock
-    res = metrics(requests)
-    res["wall_s"] = time.perf_counter() - t0
-    return res
+
+    def close(self):
+        for s, _, _ in self.members.values():
+            s.close()
+        self.members.clear()
+
+
+def run_sequential(requests: List[Request], capacity_bytes: int, device="cuda:0",
+                   cfl: float = 0.1, quantum: int = 10) -> dict:
+    """The plain path for comparison: requests run one at a time in arrival
+    order on the wall clock (set-up included), through the same Server loop."""
+    ex = SequentialExecutor(device=device, cfl=cfl)
+    try:
+        return Server(ex, capacity_bytes, max_members=1, quantum=quantum,
+                      policy="fifo").run(requests)
+    finally:
+        ex.close()

@@ -1,4 +1,4 @@
-"""Batched serving on the GPU: members advanced by graph replay give bitwise
+"""Batched serving on the GPU: members advanced by batched launches give bitwise
 the same states as the same requests run alone; completions are reported per
 member; a failing member does not disturb the others; the request loop
 completes a small Poisson mix."""
@@ -112,8 +112,8 @@ def test_request_loop_completes_mix(torch):
 def test_batch_admission_mid_run_matches_solo(torch):
     """Continuous batching: a member admitted after the others have stepped, and a
     member that completes while the others go on, each end bitwise equal to the
-    same request run alone (members never exchange data; the graph is
-    re-captured around them)."""
+    same request run alone (members never exchange data; the descriptor tables
+    are rewritten around them)."""
     from paper_2308_06196_amd import bgk
     _say("batch mid-run admission")
     stream = torch.cuda.Stream()
@@ -152,13 +152,13 @@ def test_batch_admission_mid_run_matches_solo(torch):
     batch.close()
 
 
-def test_batch_many_recaptures_between_polls(torch):
-    """More than 16 membership changes without a poll: replaced graphs pile up
-    until the batch synchronises its stream and releases them (the bound on
-    graphs held between polls); every member still ends bitwise equal to its
-    solo run."""
+def test_batch_table_churn_between_polls(torch):
+    """Twenty membership changes without a poll: every change rewrites the
+    descriptor tables through the two pinned staging buffers in turn (the
+    host waits for the copy out of a buffer before refilling it); every member
+    still ends bitwise equal to its solo run."""
     from paper_2308_06196_amd import bgk
-    _say("batch recapture churn")
+    _say("batch table churn")
     stream = torch.cuda.Stream()
     pb_long, kind_long, args_long, _ = MIX[1]
     pb_short, kind_short, args_short, _ = MIX[0]
@@ -185,4 +185,59 @@ def test_batch_many_recaptures_between_polls(torch):
     assert np.array_equal(long_m.get_state().cpu().numpy(), ref_long)
     for m in shorts:
         assert np.array_equal(m.get_state().cpu().numpy(), ref_short)
+    batch.close()
+
+
+def test_batch_families_walls_and_fp32_match_solo_bitwise(torch):
+    """Several members of one kernel family in one launch (work-unit lists
+    with several ranges), a diffuse-wall channel (wall flux and density
+    launches) and FP32 storage next to FP64: every member bitwise equal to its
+    solo run. Hexahedra and BF16 increments are refused with
+    BGK_ERR_UNSUPPORTED."""
+    from paper_2308_06196_amd import bgk
+    _say("batch families, walls, fp32")
+    cases = [
+        (wl.box2d(n=6, order=3, nv1=8, kn=1e-2), "box2d", {"amp": 0.05}, 6, bgk.FP64),
+        (wl.box2d(n=9, order=3, nv1=8, kn=3e-2), "box2d", {"amp": 0.1}, 5, bgk.FP64),
+        (wl.box2d(n=4, order=3, nv1=12, kn=1e-3), "box2d", {"amp": 0.02}, 7, bgk.FP64),
+        (wl.channel2d(nx=6, ny=6, order=2, nv1=12, kn=1e-2, uw=0.2, theta_w=1.1), "channel2d",
+         {"amp": 0.05, "k": 1, "phase": 0.2}, 6, bgk.FP64),
+        (wl.channel2d(nx=5, ny=5, order=2, nv1=8, kn=3e-2, uw=0.1, theta_w=0.9), "channel2d",
+         {"amp": 0.02, "k": 2, "phase": 1.2}, 4, bgk.FP64),
+        (wl.box2d(n=6, order=3, nv1=8, kn=1e-2), "box2d", {"amp": 0.05}, 6, bgk.FP32),
+        (wl.sod1d(nelem=40, order=2, nv1=8, kn=1e-2), "sod1d",
+         {"amp": 0.1, "k": 2, "phase": 0.3}, 9, bgk.FP32),
+    ]
+    stream = torch.cuda.Stream()
+    solo = []
+    for pb, kind, args, n, prec in cases:
+        s, dt = _solver(torch, pb, kind, args, stream, precision=prec)
+        s.rk3_step(dt, n)
+        solo.append(s.get_state().cpu().numpy())
+        s.close()
+    batch = bgk.Batch(stream, 8)
+    members = []
+    for pb, kind, args, n, prec in cases:
+        s, dt = _solver(torch, pb, kind, args, stream, precision=prec)
+        batch.add(s, dt, n)
+        members.append(s)
+    got = {}
+    for _ in range(20):
+        batch.step(3)
+        for s, err in batch.poll():
+            assert err is None
+            got[members.index(s)] = s.get_state().cpu().numpy()
+        if batch.size() == 0:
+            break
+    assert len(got) == len(cases)
+    for i in range(len(cases)):
+        assert np.array_equal(got[i], solo[i]), i
+    for pb, prec in ((wl.tgv3d(n=2, order=1, nv1=8), bgk.FP64),
+                     (wl.box2d(n=4, order=2, nv1=8), bgk.BF16)):
+        s = bgk.Solver(pb, precision=prec, stream=stream)
+        s.set_maxwellian(wl.PRIM["tgv3d" if pb["dim"] == 3 else "box2d"](s.node_coords()))
+        with pytest.raises(bgk.BGKError) as exc:
+            batch.add(s, 1e-3, 2)
+        assert exc.value.status == 2  # BGK_ERR_UNSUPPORTED
+        s.close()
     batch.close()
