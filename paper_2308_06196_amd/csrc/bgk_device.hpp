@@ -100,6 +100,15 @@ struct alignas(16) LineOps {
 };
 constexpr int kLineOpsFloats = (int)(sizeof(LineOps) / sizeof(float));
 
+// Entries of an element's equilibrium rows that one work-group reads: the
+// factors of the velocity nodes its slots use on each axis (node ranges
+// [x0, x0 + nx), [y0, y0 + ny), [z0, z0 + nz)) and 1/tau; ncols = nx + ny +
+// nz + 1 entries per spatial node, magic = ceil(2^32 / ncols) for the
+// division of a compact index by ncols.
+struct RowCols {
+  int32_t x0, nx, y0, ny, z0, nz, ncols, magic;
+};
+
 struct StageArgs {
   DevGeom g;
   DevOps op;
@@ -128,6 +137,10 @@ struct StageArgs {
   const uint16_t* din;
   int32_t out_full;
   LineOps lops;  // FR line operators for the matrix-core contraction (FP32)
+  // row entries read by velocity chunk c: rcols[c & rc_mask] (rc_mask 0: one
+  // entry for every chunk)
+  const RowCols* rcols;
+  int32_t rc_mask;
 };
 
 // BF16 <-> FP32: the upper half of the FP32 bit pattern; rounding to nearest,
@@ -394,21 +407,58 @@ __device__ __forceinline__ const DevOpsT<CT>& ops_of(const StageArgs& A) {
   else return A.opf;
 }
 
-// Equilibrium rows (FP64) from index kU * kBlock on (the first kU * kBlock
-// entries are loaded with the bulk loads) -> LDS.
+// The row entries a work-group loads, numbered compactly: entry t is node
+// a = t / ncols, column c = t - a ncols of the needed ones (x factors, y
+// factors, z factors, 1/tau). It is read from offset(t) = a S + column of the
+// element's rows and kept at LDS index t, so a node's entries in LDS are a
+// row of ncols values: x factor of velocity node bx at bx - x0, y factor at
+// nx + by - y0, z factor at nx + ny + bz - z0, 1/tau last. t / ncols is the
+// high word of t magic, exact while t ncols < 2^32 (t < 8192 entries of 8 B
+// fit LDS).
+struct RowPick {
+  int S, x0, y0, z0, oy, oz, nx, nxy, nxyz, ncols, count;
+  uint32_t magic;
+  __device__ __forceinline__ int offset(int t) const {
+    const int a = (int)__umulhi((unsigned)t, magic);
+    const int c = t - a * ncols;
+    const int col = c < nx ? x0 + c : c < nxy ? oy + (c - nx) : c < nxyz ? oz + (c - nxy) : S - 1;
+    return a * S + col;
+  }
+};
+
+__device__ __forceinline__ RowPick row_pick(const StageArgs& A, int chunk, int ns) {
+  const RowCols rc = A.rcols[chunk & A.rc_mask];  // global memory: scalar loads
+  RowPick r;
+  r.S = A.g.tabw;
+  r.x0 = rc.x0;
+  r.y0 = rc.y0;
+  r.z0 = rc.z0;
+  r.oy = A.g.nv1[0] + rc.y0;
+  r.oz = A.g.nv1[0] + A.g.nv1[1] + rc.z0;
+  r.nx = rc.nx;
+  r.nxy = rc.nx + rc.ny;
+  r.nxyz = rc.nx + rc.ny + rc.nz;
+  r.ncols = rc.ncols;
+  r.magic = (uint32_t)rc.magic;
+  r.count = ns * rc.ncols;
+  return r;
+}
+
+// Row entries from compact index kU * kBlock on (the first kU * kBlock are
+// loaded with the bulk loads) -> LDS index t.
 template <int kU>
-__device__ __forceinline__ void table_rest(double* tab, const double* et, int ntab) {
-  for (int t0 = kU * kBlock; t0 < ntab; t0 += kU * kBlock) {
+__device__ __forceinline__ void table_rest(double* tab, const double* et, const RowPick& rp) {
+  for (int t0 = kU * kBlock; t0 < rp.count; t0 += kU * kBlock) {
     double v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = t0 + u * kBlock + (int)threadIdx.x;
-      v[u] = et[t < ntab ? t : ntab - 1];
+      v[u] = et[rp.offset(t < rp.count ? t : rp.count - 1)];
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = t0 + u * kBlock + (int)threadIdx.x;
-      if (t < ntab) tab[t] = v[u];
+      if (t < rp.count) tab[t] = v[u];
     }
   }
 }
@@ -754,15 +804,15 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   // 142 instead of 213 VGPRs at p = 3 in FP64, three waves per SIMD); (3) f^n
   // after the transport. Every lane loads (clamped index, no branch): a
   // conditional load makes the compiler wait for it right there.
-  constexpr int kU = DIM == 3 ? 4 : 8;
-  const int ntab = NS * S;
+  constexpr int kU = 2;  // covers the row entries of a 1-D or 2-D chunk (ns x ncols <= 512)
+  const RowPick rp = row_pick(A, chunk, NS);
   const double* et = A.etab + node0 * S;
   double tv[kU];
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
-      tv[u] = et[t < ntab ? t : ntab - 1];
+      tv[u] = et[rp.offset(t < rp.count ? t : rp.count - 1)];
     }
   }
   // BF16-increment stages 2-3: the input is F + increment (same offsets).
@@ -794,12 +844,12 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
       for (int i = 0; i < NS; ++i) nbv[0][i] += bf16_f32(ds[i * kVB]);
     }
   }
-  // equilibrium rows (NS x S) of this element -> LDS
+  // the needed entries of this element's equilibrium rows -> LDS
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
-      if (t < ntab) tab[t] = tv[u];
+      if (t < rp.count) tab[t] = tv[u];
     }
   }
 
@@ -951,7 +1001,9 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   // relaxation sits in the one branch that loads the rows (keeping it there
   // lets the compiler overlap the LDS reads of all nodes without holding them
   // across the branch).
-  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
+  // positions of this velocity's factors in a node's LDS row (compact)
+  const int cx = vel.b[0] - rp.x0, oy = rp.nx + vel.b[1] - rp.y0,
+            oz = rp.nxy + vel.b[2] - rp.z0;
   double* oe1 = nullptr;  // residual output (canonical layout, MODE 1)
   if constexpr (MODE == 1) {
     const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
@@ -963,11 +1015,11 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   if (A.collide) {  // uniform; one branch, so the LDS reads of all nodes overlap
     // rows beyond the first batch (large velocity grids), loaded only now so
     // that their loop does not hold back the waits of the bulk loads
-    table_rest<kU>(tab, et, ntab);
+    table_rest<kU>(tab, et, rp);
     lds_barrier();
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      const double c = collision_term(tab + i * S, vel.b[0], oy, oz, S, (double)f[i]);
+      const double c = collision_term(tab + i * rp.ncols, cx, oy, oz, rp.ncols, (double)f[i]);
       if constexpr (MODE == 1) {
         if (valid) oe1[(int64_t)i * nv] = c - (double)acc[i];
       } else if constexpr (kMfma) {

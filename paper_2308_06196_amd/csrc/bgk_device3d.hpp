@@ -180,17 +180,18 @@ __global__ void __launch_bounds__(kBlock)
 
   // loads: equilibrium rows (first batch), own plane, the x-, y- and
   // z-neighbours' planes, f^n plane
-  // first batch of row loads (FP64 values: 8 x 256 for FP32 arithmetic, whose
-  // registers are scarcer; 16 x 256 covers the 16^3 grid at p = 3 in FP64)
-  constexpr int kU = P == 3 && !kMfma ? 16 : 8;
-  const int ntab = NS * S;
+  // first batch of row loads: 4 x 256 entries for FP32 arithmetic, whose
+  // registers are scarcer, 6 x 256 in FP64 (a 64-velocity chunk of the 16^3
+  // grid at p = 3 needs 64 x 22)
+  constexpr int kU = kMfma ? 4 : 6;
+  const RowPick rp = row_pick(A, chunk, NS);
   const double* et = A.etab + node0 * S;
   double tv[kU];
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {  // clamped, unconditional loads
       const int t = u * kBlock + (int)threadIdx.x;
-      tv[u] = et[t < ntab ? t : ntab - 1];
+      tv[u] = et[rp.offset(t < rp.count ? t : rp.count - 1)];
     }
   }
   // BF16-increment stages 2-3: the input is F + increment (same offsets)
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int t = u * kBlock + (int)threadIdx.x;
-      if (t < ntab) tab[t] = tv[u];
+      if (t < rp.count) tab[t] = tv[u];
     }
   }
 
@@ -336,8 +337,10 @@ __global__ void __launch_bounds__(kBlock)
   // relaxation and RK combination (as in k_stage: the collision term in
   // FP64 from the FP64 rows; FP32 arithmetic adds it to the FP32 combination
   // in FP64), all inside the branch that loads the rows
-  const int oy = g.nv1[0] + vel.b[1], oz = g.nv1[0] + g.nv1[1] + vel.b[2];
-  const double* tp = tab + pl * P2 * S;  // rows of this lane's plane
+  // positions of this velocity's factors in a node's LDS row (compact)
+  const int cx = vel.b[0] - rp.x0, oy = rp.nx + vel.b[1] - rp.y0,
+            oz = rp.nxy + vel.b[2] - rp.z0;
+  const double* tp = tab + pl * P2 * rp.ncols;  // rows of this lane's plane
   double* oe1 = nullptr;                 // residual output (MODE 1)
   if constexpr (MODE == 1) {
     const int jc = vel.b[0] + g.nv1[0] * (vel.b[1] + g.nv1[1] * vel.b[2]);
@@ -347,11 +350,11 @@ __global__ void __launch_bounds__(kBlock)
   const double wc = A.b * A.dt;
   CT o[P2];
   if (A.collide) {  // uniform: rows beyond the first batch, then the relaxation
-    table_rest<kU>(tab, et, ntab);
+    table_rest<kU>(tab, et, rp);
     lds_barrier();
 #pragma unroll
     for (int q = 0; q < P2; ++q) {
-      const double c = collision_term(tp + q * S, vel.b[0], oy, oz, S, (double)f[q]);
+      const double c = collision_term(tp + q * rp.ncols, cx, oy, oz, rp.ncols, (double)f[q]);
       if constexpr (MODE == 1) {
         if (act) oe1[(int64_t)q * nv] = c - (double)acc[q];
       } else if constexpr (kMfma) {

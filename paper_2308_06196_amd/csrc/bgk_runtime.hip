@@ -160,7 +160,8 @@ void gauss_nodes(int n1, double* xi) {
 }
 
 struct Layout {
-  size_t f[3], partials, params, etab, order, Q, prim, diag, wallp, wall_part, wall_rho, total;
+  size_t f[3], partials, params, etab, order, rcols, Q, prim, diag, wallp, wall_part, wall_rho,
+      total;
   int64_t nx, nv, ne, nvb;
   int ns, nchunk;
   int64_t wall_points;  // flux points on diffuse walls
@@ -265,6 +266,8 @@ Layout layout_of(const bgk_problem* pb) {
                              sizeof(double));
   L.order = off;
   off = align_up(off + (size_t)L.ne * sizeof(int32_t));
+  L.rcols = off;
+  off = align_up(off + (size_t)L.nchunk * sizeof(RowCols));
   L.Q = off;
   off = align_up(off + (size_t)L.nx * 5 * sizeof(double));
   L.prim = off;
@@ -311,8 +314,10 @@ struct bgk_solver {
   double* params() const { return (double*)(ws + L.params); }
   double* etab() const { return (double*)(ws + L.etab); }
   int32_t* order() const { return (int32_t*)(ws + L.order); }
+  RowCols* rcols() const { return (RowCols*)(ws + L.rcols); }
   bool order_ready = false;
   std::vector<int32_t> order_host;  // traversal order (empty: lexicographic)
+  std::vector<RowCols> rcols_host;  // row entries per velocity chunk (empty: all)
   std::vector<double> wallp_host;   // [k][s][8] diffuse-wall constants (empty: none)
   WallArgs wall;                    // sides of the diffuse walls (fin set per stage)
   double* wallp() const { return (double*)(ws + L.wallp); }
@@ -325,6 +330,42 @@ struct bgk_solver {
 };
 
 namespace {
+
+// Row entries read by the velocity slots [j0, j1): per axis the range of
+// velocity nodes they use, and 1/tau.
+RowCols row_cols(const DevGeom& g, int j0, int j1) {
+  int lo[3] = {g.nv1[0], g.nv1[1], g.nv1[2]}, hi[3] = {-1, -1, -1};
+  for (int j = j0; j < j1; ++j) {
+    int b[3];
+    slot_nodes(g, j, b);
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], b[k]);
+      hi[k] = std::max(hi[k], b[k]);
+    }
+  }
+  RowCols r;
+  r.x0 = lo[0];
+  r.nx = hi[0] - lo[0] + 1;
+  r.y0 = lo[1];
+  r.ny = hi[1] - lo[1] + 1;
+  r.z0 = lo[2];
+  r.nz = hi[2] - lo[2] + 1;
+  r.ncols = r.nx + r.ny + r.nz + 1;
+  r.magic = (int32_t)(uint32_t)(((1ull << 32) + r.ncols - 1) / r.ncols);
+  return r;
+}
+
+// Every row entry (all velocity nodes of every axis, and 1/tau).
+RowCols row_cols_all(const DevGeom& g) {
+  RowCols r;
+  r.x0 = r.y0 = r.z0 = 0;
+  r.nx = g.nv1[0];
+  r.ny = g.nv1[1];
+  r.nz = g.nv1[2];
+  r.ncols = g.tabw;
+  r.magic = (int32_t)(uint32_t)(((1ull << 32) + r.ncols - 1) / r.ncols);
+  return r;
+}
 
 StageArgs stage_args(const bgk_solver* s) {
   StageArgs A;
@@ -362,6 +403,8 @@ StageArgs stage_args(const bgk_solver* s) {
   A.params = s->params();
   A.etab = s->etab();
   A.order = s->order_host.empty() ? nullptr : s->order();
+  A.rcols = s->rcols();
+  A.rc_mask = s->rcols_host.empty() ? 0 : -1;
   A.partials = s->partials();
   A.diag = s->diag();
   A.e0 = 0;
@@ -413,6 +456,11 @@ bgk_status ensure_counters(bgk_solver* s) {
     if (!s->order_host.empty()) {
       HIP_TRY(hipMemcpyAsync(s->order(), s->order_host.data(),
                              s->order_host.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             s->stream));
+    }
+    if (!s->rcols_host.empty()) {
+      HIP_TRY(hipMemcpyAsync(s->rcols(), s->rcols_host.data(),
+                             s->rcols_host.size() * sizeof(RowCols), hipMemcpyHostToDevice,
                              s->stream));
     }
     if (!s->wallp_host.empty()) {
@@ -605,9 +653,10 @@ namespace {
 
 // Fill a solver object for problem *pb over the device memory ws (a validated
 // problem). With brick = false the elements are visited in lexicographic
-// order (results are the same bit for bit; the brick order only improves
-// cache reuse of hexahedral neighbours) and, without diffuse walls, the
-// host side allocates nothing.
+// order and every work-group loads all entries of its element's equilibrium
+// rows (results are the same bit for bit; the brick order and the per-chunk
+// row entries only save memory traffic) and, without diffuse walls, the host
+// side allocates nothing.
 void init_solver(bgk_solver* s, const bgk_problem* pb, char* ws, hipStream_t stream, bool brick) {
   s->pb = *pb;
   s->L = layout_of(pb);
@@ -642,6 +691,13 @@ void init_solver(bgk_solver* s, const bgk_problem* pb, char* ws, hipStream_t str
   set_velocity_slots(g, !(pb->dim == 3 && pb->precision == BGK_FP64));
   build_ops(g.n1, g.dim, s->op);
   if (brick && pb->dim == 3) brick_order(g.nelem, s->order_host);
+  if (brick) {
+    // the row entries each velocity chunk of the stage kernels reads
+    const int vb = velocities_per_block(pb->dim, pb->order, pb->precision);
+    s->rcols_host.resize(g.nchunk);
+    for (int c = 0; c < g.nchunk; ++c)
+      s->rcols_host[c] = row_cols(g, c * vb, (int)std::min<int64_t>((int64_t)(c + 1) * vb, g.nv));
+  }
   setup_walls(s);
 }
 
@@ -1105,6 +1161,11 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int64_t
   if (i < n) p[i] = v;
 }
 
+// Store one row-entry descriptor (a kernel, for the same reason).
+__global__ void k_store_rowcols(RowCols* p, RowCols v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
 namespace {
 
 constexpr int kMaxDevices = 64;
@@ -1144,6 +1205,8 @@ Layout residual_layout(const bgk_problem* pb) {
                            sizeof(double));
   L.diag = off;
   off = align_up(off + 8 * sizeof(unsigned long long));
+  L.rcols = off;  // one entry (every row entry) for every velocity chunk
+  off = align_up(off + sizeof(RowCols));
   L.order = L.Q = L.prim = L.wallp = L.wall_part = L.wall_rho = off;
   L.total = off;
   return L;
@@ -1174,6 +1237,9 @@ bgk_status bgk_residual_noalloc(const bgk_problem* pb, const double* f_in, doubl
   init_solver(&s, pb, (char*)base, (hipStream_t)hip_stream, false);
   s.L = L;
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, s.stream, s.diag(), (int64_t)8, 0ull);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_store_rowcols, dim3(1), dim3(64), 0, s.stream, s.rcols(),
+                     row_cols_all(s.g));
   HIP_TRY(hipGetLastError());
   const int64_t n = L.nx * L.nv;
   HIP_TRY(launch_to_storage(s.precision, s.g, f_in, s.f(0), 0, n, s.stream));
