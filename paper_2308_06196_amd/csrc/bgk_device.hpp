@@ -683,12 +683,15 @@ __device__ __forceinline__ bool quads_agree(bool pos) {
 // with FP32 storage (6-7 % faster than 4 on the 32^2 p = 3 box), 4 with BF16
 // increments (whose second value per neighbour node spills at 5, which
 // doubled the time), 3 in FP64; hexahedra (one lane per velocity with all
-// (p+1)^3 nodes, FP32 storage) 3 at p = 2 and 2 at p = 3 (measured: a few
-// spilled registers at p = 3 cost less than halving the waves; at p = 2 four
-// waves' spills cost a third of the time).
+// (p+1)^3 nodes) 3 at p = 2 in FP32 arithmetic and 2 in FP64 (three spill
+// and took 2.5x as long), 2 at p = 3 (measured: a few spilled registers at
+// p = 3 cost less than halving the waves; at p = 2 four waves' spills cost a
+// third of the time).
 template <int DIM, int P, typename CT, bool INC>
 constexpr int stage_waves() {
-  return DIM == 3 && P == 3 ? 2 : DIM == 3 && P == 2 ? 3 : sizeof(CT) == 8 ? 3 : INC ? 4 : 5;
+  return DIM == 3 && P == 3 ? 2
+         : DIM == 3 && P == 2 ? (sizeof(CT) == 8 ? 2 : 3)
+         : sizeof(CT) == 8 ? 3 : INC ? 4 : 5;
 }
 
 // ---------------------------------------------------------------------------

@@ -504,6 +504,70 @@ __global__ void __launch_bounds__(256) k_to_canonical(const DevGeom g, const SRC
 // ---------------------------------------------------------------------------
 static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Hexahedra. The one-lane-per-velocity kernels (k_stage<3, ...>: all
+// (p+1)^3 nodes of a velocity in one lane's registers) run FP32 storage at
+// every order and FP64 storage and BF16 increments at p <= 2; the
+// plane-split kernels (k_stage3: four lanes per velocity, one z-plane each)
+// run FP64 storage and BF16 increments at p = 3, where one lane cannot hold
+// the element (FP64) or the second value per neighbour node (BF16: 137
+// spilled registers). On the 16^3-element Taylor-Green box, ms per stage,
+// plane-split against one-lane: FP64 p = 1 1.18 / 0.82, p = 2 4.95 / 2.50
+// (two waves per SIMD; 6.22 at three, which spill); BF16 p = 1 0.90 / 0.51,
+// p = 2 3.31 / 1.62, p = 3 6.83 / 7.72; FP32 p = 3 5.49 / 3.61.
+// The choice (hex_one_lane) is per solver, so that all its kernels share one
+// velocity-chunk width; it must agree with kHexOneLane below.
+template <int P, typename ST>
+constexpr bool kHexOneLane(bool inc) {
+  return sizeof(ST) == 8 ? P <= 2 : (P <= 2 || !inc);
+}
+
+template <int P, typename ST>
+static hipError_t hex_dispatch(int mode, bool inc, const StageArgs& A, size_t tab, size_t lds,
+                               dim3 grid, dim3 block, hipStream_t s) {
+  if (kHexOneLane<P, ST>(inc)) {
+    if constexpr (sizeof(ST) == 8 && P > 2) return hipErrorInvalidValue;  // not built
+    else {
+      if (mode == 0 && inc) {
+        if constexpr (sizeof(ST) == 4 && P <= 2) {
+          if (A.din)
+            hipLaunchKernelGGL((k_stage<3, P, ST, 0, true>), grid, block, lds, s, A);
+          else
+            hipLaunchKernelGGL((k_stage<3, P, ST, 3, true>), grid, block, lds, s, A);
+        }
+      } else if (mode == 0 && A.a != 0.0) {
+        hipLaunchKernelGGL((k_stage<3, P, ST, 0>), grid, block, lds, s, A);
+      } else if (mode == 0) {
+        hipLaunchKernelGGL((k_stage<3, P, ST, 3>), grid, block, lds, s, A);
+      } else if (mode == 1) {
+        hipLaunchKernelGGL((k_stage<3, P, ST, 1>), grid, block, lds, s, A);
+      } else {
+        hipLaunchKernelGGL((k_moments<3, P, ST>), grid, block, lds, s, A);
+      }
+      return hipGetLastError();
+    }
+  }
+  // plane-split; the FP64 ones decode lexicographic slots (one octant)
+  if (sizeof(ST) == 8 && A.g.voct[7] != 0) return hipErrorInvalidValue;
+  const size_t lds3 = mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab;
+  if (mode == 0 && inc) {
+    if constexpr (sizeof(ST) == 4) {
+      if (A.din)
+        hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3, s, A);
+      else
+        hipLaunchKernelGGL((k_stage3<P, ST, 3, true>), grid, block, lds3, s, A);
+    }
+  } else if (mode == 0 && A.a != 0.0) {
+    hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds3, s, A);
+  } else if (mode == 0) {
+    hipLaunchKernelGGL((k_stage3<P, ST, 3>), grid, block, lds3, s, A);
+  } else if (mode == 1) {
+    hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds3, s, A);
+  } else {
+    hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, lds3, s, A);
+  }
+  return hipGetLastError();
+}
+
 template <typename ST>
 static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStream_t s) {
   const dim3 grid((unsigned)(A.g.nchunk * A.ecount)), block(kBlock);
@@ -532,51 +596,9 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
     else                                                                   \
       hipLaunchKernelGGL((k_moments<D, P, ST>), grid, block, lds, s, A);   \
     break;
-// Hexahedra: FP32 storage runs the one-lane-per-velocity kernels (all
-// (p+1)^3 nodes of the element in one lane's registers); FP64 storage, and
-// BF16 increments (which add a second value per neighbour node), the
-// plane-split kernels, whose lanes hold one z-plane each. The choice is per
-// solver, so that all its kernels share one velocity-chunk width.
 #define BGK_CASE3(P)                                                       \
-  case 30 + P: {                                                           \
-    if constexpr (sizeof(ST) == 4) {                                       \
-      if (inc) {                                                           \
-        const size_t lds3i =                                               \
-            mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
-        if (mode == 0 && A.din)                                            \
-          hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3i, s, A); \
-        else if (mode == 0)                                                \
-          hipLaunchKernelGGL((k_stage3<P, ST, 3, true>), grid, block, lds3i, s, A); \
-        else if (mode == 1)                                                \
-          hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds3i, s, A); \
-        else                                                               \
-          hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, lds3i, s, A); \
-        break;                                                             \
-      }                                                                    \
-      if (mode == 0 && A.a != 0.0)                                         \
-        hipLaunchKernelGGL((k_stage<3, P, ST, 0>), grid, block, lds, s, A); \
-      else if (mode == 0)                                                  \
-        hipLaunchKernelGGL((k_stage<3, P, ST, 3>), grid, block, lds, s, A); \
-      else if (mode == 1)                                                  \
-        hipLaunchKernelGGL((k_stage<3, P, ST, 1>), grid, block, lds, s, A); \
-      else                                                                 \
-        hipLaunchKernelGGL((k_moments<3, P, ST>), grid, block, lds, s, A); \
-      break;                                                               \
-    }                                                                      \
-    /* FP64 plane-split kernels decode lexicographic slots (one octant) */ \
-    if (sizeof(ST) == 8 && A.g.voct[7] != 0) return hipErrorInvalidValue; \
-    const size_t lds3 =                                                    \
-        mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab; \
-    if (mode == 0 && A.a != 0.0)                                           \
-      hipLaunchKernelGGL((k_stage3<P, ST, 0>), grid, block, lds3, s, A);   \
-    else if (mode == 0)                                                    \
-      hipLaunchKernelGGL((k_stage3<P, ST, 3>), grid, block, lds3, s, A);   \
-    else if (mode == 1)                                                    \
-      hipLaunchKernelGGL((k_stage3<P, ST, 1>), grid, block, lds3, s, A);   \
-    else                                                                   \
-      hipLaunchKernelGGL((k_moments3<P, ST>), grid, block, lds3, s, A);    \
-    break;                                                                 \
-  }
+  case 30 + P:                                                             \
+    return hex_dispatch<P, ST>(mode, inc, A, tab, lds, grid, block, s);
   switch (key) {
     BGK_CASE(1, 1) BGK_CASE(1, 2) BGK_CASE(1, 3)
     BGK_CASE(2, 1) BGK_CASE(2, 2) BGK_CASE(2, 3)
@@ -589,8 +611,12 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
   return hipGetLastError();
 }
 
+bool hex_one_lane(int order, int precision) {
+  return precision != 2 ? (precision == 1 || order <= 2) : order <= 2;
+}
+
 int velocities_per_block(int dim, int order, int precision) {
-  if (dim < 3 || precision == 1) return kBlock;
+  if (dim < 3 || hex_one_lane(order, precision)) return kBlock;
   return order + 1 <= 2 ? Plane3<1>::VB : Plane3<3>::VB;
 }
 

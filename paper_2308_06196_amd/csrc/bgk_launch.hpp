@@ -14,6 +14,9 @@ namespace bgk {
 // Velocities covered by one work-group of the stage kernel (the moment
 // partials are per such chunk).
 int velocities_per_block(int dim, int order, int precision);
+// Hexahedra of this order and storage precision run the one-lane-per-velocity
+// stage kernels (else the plane-split ones).
+bool hex_one_lane(int order, int precision);
 
 // mode 0: fused RK stage (a variant that does not read f^n when a = 0);
 // 1: residual L(f) in FP64; 2: moment partials only.

@@ -685,10 +685,11 @@ void init_solver(bgk_solver* s, const bgk_problem* pb, char* ws, hipStream_t str
   g.nvb = s->L.nvb;
   g.nchunk = s->L.nchunk;
   // velocity slots: octants of the signs of the transported components. FP64
-  // hexahedra keep the lexicographic order (no split): their plane-split
-  // kernels measured 4 % faster with it on the 16^3 x 16^3 Taylor-Green box,
-  // where the FP32 hexahedra ran 6 % faster with the octants.
-  set_velocity_slots(g, !(pb->dim == 3 && pb->precision == BGK_FP64));
+  // hexahedra on the plane-split kernels keep the lexicographic order (no
+  // split): they measured 4 % faster with it on the 16^3 x 16^3 Taylor-Green
+  // box, where the one-lane FP32 hexahedra ran 6 % faster with the octants.
+  set_velocity_slots(g, !(pb->dim == 3 && pb->precision == BGK_FP64 &&
+                          !hex_one_lane(pb->order, pb->precision)));
   build_ops(g.n1, g.dim, s->op);
   if (brick && pb->dim == 3) brick_order(g.nelem, s->order_host);
   if (brick) {
