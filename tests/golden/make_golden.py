@@ -1,0 +1,64 @@
+"""Write the oracle's long-run moment fixtures (FP64 CPU oracle only).
+
+    python tests/golden/make_golden.py [box2d] [tgv3d_n8]
+
+Each fixture is the oracle's per-node moments Q [nx][5] = (rho, rho U, E)
+after a full run, stored as ``<name>_q.npy`` with ``<name>.json`` beside it
+(problem, time step, steps, oracle diagnostics, wall time). Inputs come from the
+seeded workload generators; every number written is the oracle's.
+
+  box2d     2-D periodic box, 32x32 elements, p = 3, 24^3 velocities on
+            [-6,6]^3, Kn = 1e-3, sampled Maxwellian initial state, CFL 0.1,
+            200 SSP-RK3 steps.
+  tgv3d_n8  3-D Taylor-Green box with the full case's order (p = 3), velocity
+            grid (16^3 on [-5,5]^3), Knudsen number and initial state on a
+            reduced mesh of 8^3 elements, 100 SSP-RK3 steps (the time step is
+            bounded by the relaxation time, as on the full mesh).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2308_06196_amd import workloads as wl  # noqa: E402
+from tests.helpers import oracle_problem  # noqa: E402
+
+
+def _run(name, pb, kind, steps, dt=None):
+    pr = oracle_problem(pb)
+    f0 = orc.maxwellian(pr, wl.PRIM[kind](orc.node_coords(pr)))
+    if dt is None:
+        dt = orc.stable_dt(pr, f0, 0.1)
+    t0 = time.time()
+    f, diag = orc.rk3_step(pr, f0, dt, steps)
+    wall = time.time() - t0
+    Q = orc.moments(pr, f)
+    np.save(os.path.join(HERE, f"{name}_q.npy"), Q)
+    meta = {"name": name, "kind": kind, "problem": pb, "dt": dt, "steps": steps,
+            "oracle_diag": diag, "oracle_wall_s": round(wall, 1),
+            "threads": os.environ.get("OMP_NUM_THREADS", "all")}
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(meta, fh, indent=1)
+    print(f"{name}: {steps} steps in {wall:.0f} s, dt {dt:.6e}, diag {diag}", flush=True)
+
+
+def box2d():
+    _run("box2d", wl.box2d(), "box2d", 200)
+
+
+def tgv3d_n8():
+    _run("tgv3d_n8", wl.tgv3d(n=8), "tgv3d", 100)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["box2d", "tgv3d_n8"]
+    for w in which:
+        {"box2d": box2d, "tgv3d_n8": tgv3d_n8}[w]()
