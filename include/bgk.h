@@ -339,15 +339,25 @@ bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, void* d_works
 bgk_status bgk_batch_add(bgk_batch* b, bgk_solver* s, double dt, int64_t nsteps);
 
 /* Queue nsteps replays (see above; a member stops after its own step count
- * and becomes pollable). Asynchronous on the batch stream. */
+ * and becomes pollable). Asynchronous on the batch stream, except that it
+ * waits while more than 8 replays are queued beyond the last one the device
+ * has completed (so a caller admitting new members between calls is never
+ * far behind the device). */
 bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps);
 
-/* Synchronise with the batch stream and hand back up to cap members that
- * have completed their steps: done[i] and its status status[i] (BGK_OK or
- * the member's numerical failure). They leave the batch; *ndone is the
- * count. */
+/* Hand back up to cap members that have completed their steps, in
+ * completion order, waiting until the device has executed their last
+ * replay: done[i] and its status status[i] (BGK_OK, or BGK_ERR_NEWTON when
+ * an equilibrium solve of the member failed; the solver is then marked
+ * failed). They leave the batch and their slots become free; *ndone is the
+ * count. Later replays may still be running when it returns. */
 bgk_status bgk_batch_poll(bgk_batch* b, bgk_solver** done, int32_t* status, int32_t cap,
                           int32_t* ndone);
+
+/* As bgk_batch_poll, but without waiting: only members whose last replay the
+ * device has already executed (possibly none). */
+bgk_status bgk_batch_poll_ready(bgk_batch* b, bgk_solver** done, int32_t* status, int32_t cap,
+                                int32_t* ndone);
 
 /* Remove an active member before completion (waits for queued work). */
 bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s);

@@ -140,6 +140,7 @@ def lib():
             "bgk_batch_add": [vp, vp, C.c_double, C.c_int64],
             "bgk_batch_step": [vp, i32],
             "bgk_batch_poll": [vp, C.POINTER(vp), C.POINTER(i32), i32, C.POINTER(i32)],
+            "bgk_batch_poll_ready": [vp, C.POINTER(vp), C.POINTER(i32), i32, C.POINTER(i32)],
             "bgk_batch_remove": [vp, vp],
             "bgk_batch_destroy": [vp],
         }
@@ -216,12 +217,16 @@ class Solver:
                                 C.c_void_p(self.stream.cuda_stream), C.byref(self._s)))
 
     # -- lifetime ------------------------------------------------------------
-    def close(self):
+    def close(self, sync: bool = True):
+        """Release the solver and its workspace. sync=False skips waiting for
+        the solver's stream: only for a solver whose work is known to have
+        completed (a batch member handed back by Batch.poll)."""
         if self._s:
             _check(lib().bgk_destroy(self._s))
             self._s = C.c_void_p()
             # queued work on the solver's stream may still use the workspace
-            self.stream.synchronize()
+            if sync:
+                self.stream.synchronize()
             self.workspace = None
 
     def __del__(self):
@@ -369,13 +374,15 @@ class Batch:
     def size(self) -> int:
         return int(lib().bgk_batch_size(self._b))
 
-    def poll(self):
-        """[(solver, None | error message)] of members that completed."""
+    def poll(self, block: bool = True):
+        """[(solver, None | error message)] of members that completed; with
+        block=False only those whose work the device has already executed."""
         cap = max(1, len(self._members))
         done = (C.c_void_p * cap)()
         st = (C.c_int32 * cap)()
         n = C.c_int32(0)
-        _check(lib().bgk_batch_poll(self._b, done, st, cap, C.byref(n)))
+        fn = lib().bgk_batch_poll if block else lib().bgk_batch_poll_ready
+        _check(fn(self._b, done, st, cap, C.byref(n)))
         out = []
         for i in range(n.value):
             s = self._members.pop(done[i])

@@ -1324,9 +1324,22 @@ struct bgk_batch {
     int dim, order, precision;
     size_t tab_bytes;  // dynamic LDS of its stage launches (equilibrium rows)
   };
+  struct Finished {
+    bgk_solver* s;
+    int64_t replay;  // the replay that completed its steps
+    int slot;        // kept until the member is polled (its counter staging)
+  };
   std::vector<Member> members;
-  std::vector<bgk_solver*> finished;  // stepped to completion, not yet polled
+  std::vector<Finished> finished;  // stepped to completion, not yet polled
   std::vector<int> free_slots;
+  // replay completion: event ev[r % kEvents] is recorded after replay r; a
+  // finished member's failure counters are copied to pinned diag[slot] ahead
+  // of that event. At most kAhead replays are queued beyond the last one known
+  // to have completed.
+  static constexpr int kEvents = 32, kAhead = 8;
+  hipEvent_t ev[kEvents] = {};
+  int64_t replays = 0;
+  unsigned long long* diag = nullptr;  // pinned [max_members][2]
   std::vector<Family> fams;           // families the lists can name
   bool tables_dirty = true;
   // work units of every list as last written: [sub][list] stage, newton,
@@ -1465,6 +1478,46 @@ void destroy_batch_host(bgk_batch* b) {
     if (b->host[h]) (void)hipHostFree(b->host[h]);
     if (b->copied[h]) (void)hipEventDestroy(b->copied[h]);
   }
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->diag) (void)hipHostFree(b->diag);
+}
+
+// Hand back finished members in completion order: all of them once their
+// replay has executed (block), or those whose replay already has (no wait).
+bgk_status batch_collect(bgk_batch* b, bgk_solver** done, int32_t* status, int32_t cap,
+                         int32_t* ndone, bool block) {
+  *ndone = 0;
+  int32_t n = 0;
+  size_t i = 0;
+  for (; i < b->finished.size() && n < cap; ++i) {
+    const bgk_batch::Finished& f = b->finished[i];
+    hipEvent_t e = b->ev[f.replay % bgk_batch::kEvents];
+    // a later record of the same event marks a later replay on the same
+    // stream, whose completion implies this one's
+    if (block) {
+      HIP_TRY(hipEventSynchronize(e));
+    } else {
+      const hipError_t q = hipEventQuery(e);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(BGK_ERR_DEVICE, "event query: %s", hipGetErrorString(q));
+    }
+    bgk_solver* s = f.s;
+    s->in_batch = false;
+    const unsigned long long nfail = b->diag[f.slot * 2 + 1];
+    int32_t st = BGK_OK;
+    if (nfail > 0) {
+      s->failed = true;
+      st = BGK_ERR_NEWTON;
+    }
+    b->free_slots.push_back(f.slot);
+    done[n] = s;
+    status[n] = st;
+    ++n;
+  }
+  b->finished.erase(b->finished.begin(), b->finished.begin() + i);
+  *ndone = n;
+  return BGK_OK;
 }
 
 }  // namespace
@@ -1508,6 +1561,15 @@ bgk_status bgk_batch_create(void* hip_stream, int32_t max_members, void* d_works
       return fail(BGK_ERR_DEVICE, "batch staging: %s", hipGetErrorString(e));
     }
     memset(b->host[h], 0, b->tl.total);
+  }
+  hipError_t e = hipHostMalloc((void**)&b->diag, (size_t)max_members * 2 * sizeof(unsigned long long),
+                               hipHostMallocDefault);
+  for (int i = 0; i < bgk_batch::kEvents && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_batch_host(b);
+    delete b;
+    return fail(BGK_ERR_DEVICE, "batch events: %s", hipGetErrorString(e));
   }
   *out = b;
   return BGK_OK;
@@ -1568,6 +1630,9 @@ bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps) {
   if (!b) return fail(BGK_ERR_INVALID_ARG, "NULL batch");
   if (nsteps < 0) return fail(BGK_ERR_INVALID_ARG, "nsteps < 0");
   for (int32_t k = 0; k < nsteps && !b->members.empty(); ++k) {
+    // keep at most kAhead replays queued beyond the last completed one
+    if (b->replays >= bgk_batch::kAhead)
+      HIP_TRY(hipEventSynchronize(b->ev[(b->replays - bgk_batch::kAhead) % bgk_batch::kEvents]));
     if (b->tables_dirty) {
       bgk_status st = upload_tables(b);
       if (st) return st;
@@ -1579,8 +1644,10 @@ bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps) {
       bgk_batch::Member& m = b->members[i];
       m.remaining -= m.per_replay;
       if (m.remaining == 0) {
-        b->finished.push_back(m.s);
-        b->free_slots.push_back(m.slot);
+        // its failure counters as of this replay, read at the poll
+        HIP_TRY(hipMemcpyAsync(b->diag + m.slot * 2, m.s->diag(), 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, b->stream));
+        b->finished.push_back({m.s, b->replays, m.slot});
         b->tables_dirty = true;
       } else {
         if (m.per_replay > m.remaining) b->tables_dirty = true;  // re-balance near the end
@@ -1588,6 +1655,8 @@ bgk_status bgk_batch_step(bgk_batch* b, int32_t nsteps) {
       }
     }
     b->members.resize(w);
+    HIP_TRY(hipEventRecord(b->ev[b->replays % bgk_batch::kEvents], b->stream));
+    ++b->replays;
   }
   return BGK_OK;
 }
@@ -1596,21 +1665,14 @@ bgk_status bgk_batch_poll(bgk_batch* b, bgk_solver** done, int32_t* status, int3
                           int32_t* ndone) {
   if (!b || !ndone || (cap > 0 && (!done || !status)))
     return fail(BGK_ERR_INVALID_ARG, "NULL argument");
-  *ndone = 0;
-  if (b->finished.empty()) return BGK_OK;
-  HIP_TRY(hipStreamSynchronize(b->stream));
-  int32_t n = 0;
-  size_t i = 0;
-  for (; i < b->finished.size() && n < cap; ++i) {
-    bgk_solver* s = b->finished[i];
-    s->in_batch = false;
-    done[n] = s;
-    status[n] = (int32_t)check_failed(s);
-    ++n;
-  }
-  b->finished.erase(b->finished.begin(), b->finished.begin() + i);
-  *ndone = n;
-  return BGK_OK;
+  return batch_collect(b, done, status, cap, ndone, true);
+}
+
+bgk_status bgk_batch_poll_ready(bgk_batch* b, bgk_solver** done, int32_t* status, int32_t cap,
+                                int32_t* ndone) {
+  if (!b || !ndone || (cap > 0 && (!done || !status)))
+    return fail(BGK_ERR_INVALID_ARG, "NULL argument");
+  return batch_collect(b, done, status, cap, ndone, false);
 }
 
 bgk_status bgk_batch_remove(bgk_batch* b, bgk_solver* s) {
@@ -1634,7 +1696,7 @@ bgk_status bgk_batch_destroy(bgk_batch* b) {
   if (!b) return BGK_OK;
   (void)hipStreamSynchronize(b->stream);
   for (auto& m : b->members) m.s->in_batch = false;
-  for (auto* s : b->finished) s->in_batch = false;
+  for (auto& f : b->finished) f.s->in_batch = false;
   destroy_batch_host(b);
   delete b;
   return BGK_OK;

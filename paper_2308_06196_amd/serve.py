@@ -202,14 +202,20 @@ class BatchExecutor(Executor):
         self.batch.step(n)
 
     def poll(self) -> list:
+        # without waiting while members are still stepping (the device keeps
+        # working on the queued replays while the server admits new requests);
+        # once none is, wait for the finished ones
         out = []
-        for s, err in self.batch.poll():
+        for s, err in self.batch.poll(block=self.batch.size() == 0):
             out.append((id(s), err))
         return out
 
     def release(self, handle) -> None:
+        # handed back by poll: the device has executed all of its work, and
+        # later replays no longer name it, so its memory is free without
+        # waiting for the batch stream
         s = self.members.pop(handle)
-        s.close()
+        s.close(sync=False)
 
     def close(self):
         self.batch.close()

@@ -241,3 +241,37 @@ def test_batch_families_walls_and_fp32_match_solo_bitwise(torch):
         assert exc.value.status == 2  # BGK_ERR_UNSUPPORTED
         s.close()
     batch.close()
+
+
+def test_batch_poll_without_waiting_matches_solo(torch):
+    """Non-blocking polls (bgk_batch_poll_ready) hand back a member only once
+    the device has executed its last replay; members released that way (no
+    stream synchronisation) end bitwise equal to their solo runs, and the
+    queue of replays ahead of the device stays bounded."""
+    from paper_2308_06196_amd import bgk
+    _say("batch poll without waiting")
+    stream = torch.cuda.Stream()
+    solo = []
+    for pb, kind, args, n in MIX:
+        s, dt = _solver(torch, pb, kind, args, stream)
+        s.rk3_step(dt, n)
+        solo.append(s.get_state().cpu().numpy())
+        s.close()
+    batch = bgk.Batch(stream, 8)
+    members = []
+    for pb, kind, args, n in MIX:
+        s, dt = _solver(torch, pb, kind, args, stream)
+        batch.add(s, dt, n)
+        members.append(s)
+    got = {}
+    for _ in range(200):
+        batch.step(1)
+        for s, err in batch.poll(block=batch.size() == 0):
+            assert err is None
+            got[members.index(s)] = s.get_state().cpu().numpy()
+        if len(got) == len(MIX):
+            break
+    assert len(got) == len(MIX)
+    for i in range(len(MIX)):
+        assert np.array_equal(got[i], solo[i]), i
+    batch.close()
