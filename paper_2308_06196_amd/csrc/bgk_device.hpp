@@ -97,6 +97,7 @@ using DevOps = DevOpsT<double>;
 struct alignas(16) LineOps {
   float Dp[2][4][4];    // [pos][row i][column k]
   float E[2][2][4][4];  // [pos][use_right][row i][column k]
+  float G[2][4];        // [pos][row i]: G_in, for a given exterior trace
 };
 constexpr int kLineOpsFloats = (int)(sizeof(LineOps) / sizeof(float));
 
@@ -141,6 +142,7 @@ struct StageArgs {
   // entry for every chunk)
   const RowCols* rcols;
   int32_t rc_mask;
+  int32_t sweep_seg;  // column sweeps: elements per work item along the last axis
 };
 
 // BF16 <-> FP32: the upper half of the FP32 bit pattern; rounding to nearest,
@@ -345,8 +347,9 @@ struct alignas(16) FaceRows {
 };
 
 template <typename CT, int N1, bool WITH_D = false>
-__device__ __forceinline__ void face_rows_store(FaceRows<CT>& fr, const DevOpsT<CT>& OP) {
-  if ((threadIdx.x & 63) == 0) {
+__device__ __forceinline__ void face_rows_store(FaceRows<CT>& fr, const DevOpsT<CT>& OP,
+                                                const int tid) {
+  if ((tid & 63) == 0) {
 #pragma unroll
     for (int b = 0; b < N1; ++b) {
       fr.r[0][b] = OP.lamR[b];
@@ -447,17 +450,18 @@ __device__ __forceinline__ RowPick row_pick(const StageArgs& A, int chunk, int n
 // Row entries from compact index kU * kBlock on (the first kU * kBlock are
 // loaded with the bulk loads) -> LDS index t.
 template <int kU>
-__device__ __forceinline__ void table_rest(double* tab, const double* et, const RowPick& rp) {
+__device__ __forceinline__ void table_rest(double* tab, const double* et, const RowPick& rp,
+                                           const int tid) {
   for (int t0 = kU * kBlock; t0 < rp.count; t0 += kU * kBlock) {
     double v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int t = t0 + u * kBlock + (int)threadIdx.x;
+      const int t = t0 + u * kBlock + tid;
       v[u] = et[rp.offset(t < rp.count ? t : rp.count - 1)];
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int t = t0 + u * kBlock + (int)threadIdx.x;
+      const int t = t0 + u * kBlock + tid;
       if (t < rp.count) tab[t] = v[u];
     }
   }
@@ -492,9 +496,9 @@ typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 // moments, would take twice the matrix-core cycles.)
 template <int NT, int NV, int K, typename ST>
 __device__ __forceinline__ void wave_moments_4x4(const ST* gw, int rs, const double* ps,
-                                                 double* redw) {
+                                                 double* redw, const int tid) {
   static_assert(NV <= 16 && K % 4 == 0, "tiles of 16 rows, velocities in fours");
-  const int lane = threadIdx.x & 63;
+  const int lane = tid & 63;
   const int k = lane >> 4, blk = (lane >> 2) & 3, j = lane & 3;
   const int ra = 4 * blk + j;  // A row of this lane inside a tile
   double d0[NT], d1[NT];
@@ -548,10 +552,10 @@ constexpr int part_rows() {
 // are reused by the next tile once this wave has read them).
 template <int T, int NS, typename ST, typename CT>
 __device__ __forceinline__ void element_tiles(const CT (&fv)[NS], ST* gw, const double* ps,
-                                              double* redw) {
+                                              double* redw, const int tid) {
   if constexpr (16 * T < NS) {
     constexpr int NV = NS - 16 * T < 16 ? NS - 16 * T : 16;
-    const int lane = threadIdx.x & 63;
+    const int lane = tid & 63;
 #pragma unroll
     for (int i = 0; i < NV; ++i) gw[i * kGst + lane] = (ST)fv[16 * T + i];
     // the lanes of this wave read what the others wrote (LDS is ordered
@@ -559,11 +563,11 @@ __device__ __forceinline__ void element_tiles(const CT (&fv)[NS], ST* gw, const 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-    wave_moments_4x4<1, NV, 64, ST>(gw, kGst, ps, redw + 16 * T * 5);
+    wave_moments_4x4<1, NV, 64, ST>(gw, kGst, ps, redw + 16 * T * 5, tid);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-    element_tiles<T + 1, NS, ST, CT>(fv, gw, ps, redw);
+    element_tiles<T + 1, NS, ST, CT>(fv, gw, ps, redw, tid);
   }
 }
 
@@ -571,9 +575,10 @@ template <int NS, typename ST, typename CT>
 __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const Vel& vel,
                                                       double* __restrict__ partials,
                                                       int64_t node0, int64_t nx, int chunk,
-                                                      unsigned char* stage, double* red) {
+                                                      unsigned char* stage, double* red,
+                                                      const int tid) {
   constexpr int NR = part_rows<NS>();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   double* ps = reinterpret_cast<double*>(stage) + wave * 64 * 5;
   ST* gw = reinterpret_cast<ST*>(stage + (kBlock / 64) * 64 * 5 * sizeof(double)) + wave * 16 * kGst;
   const double psi4 = 0.5 * (vel.u[0] * vel.u[0] + vel.u[1] * vel.u[1] + vel.u[2] * vel.u[2]);
@@ -582,9 +587,9 @@ __device__ __forceinline__ void element_partials_mfma(const CT (&fv)[NS], const 
   ps[lane * 5 + 2] = vel.w * vel.u[1];
   ps[lane * 5 + 3] = vel.w * vel.u[2];
   ps[lane * 5 + 4] = vel.w * psi4;
-  element_tiles<0, NS, ST, CT>(fv, gw, ps, red + wave * NR * 5);
+  element_tiles<0, NS, ST, CT>(fv, gw, ps, red + wave * NR * 5, tid);
   lds_barrier();
-  for (int t = threadIdx.x; t < 5 * NS; t += kBlock) {
+  for (int t = tid; t < 5 * NS; t += kBlock) {
     const int node = t / 5, m = t - node * 5;
     double sum = red[node * 5 + m];
 #pragma unroll
@@ -646,10 +651,40 @@ __device__ __forceinline__ mfma_f4 line_mfma(const float (&dp)[4], const float (
   return c;
 }
 
+// The own part Dp f_own of one line (see line_mfma).
+template <int N1>
+__device__ __forceinline__ mfma_f4 line_mfma_own(const float (&dp)[4], const float (&fl)[N1]) {
+  mfma_f4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < N1; ++k) c = __builtin_amdgcn_mfma_f32_4x4x1f32(dp[k], fl[k], c, 0, 0, 0);
+  return c;
+}
+
+// Column sweep: the outflow traces of the element's lines along the last
+// axis (stride NT between the nodes of a line), sum_b lout[b] f(line node b),
+// lout = lamR where the sweep runs towards +x_k (the downwind element's
+// exterior trace is this element's right trace) and lamL otherwise; kept in
+// registers (tr) or in this lane's column of trl.
+template <int N1, int NT, bool LDS, typename CT, int NS, int R>
+__device__ __forceinline__ void sweep_store(const CT* lout, const CT (&f)[NS], CT* trl,
+                                            CT (&tr)[R], const int tid) {
+  CT lo[N1];
+#pragma unroll
+  for (int bb = 0; bb < N1; ++bb) lo[bb] = lout[bb];
+#pragma unroll
+  for (int base = 0; base < NT; ++base) {
+    CT t = (CT)0;
+#pragma unroll
+    for (int bb = 0; bb < N1; ++bb) t += lo[bb] * f[base + bb * NT];
+    if constexpr (LDS) trl[base * kBlock + tid] = t;
+    else tr[base] = t;
+  }
+}
+
 // Copy the line operators to this wave's LDS copy (read back through per-lane
 // addresses).
-__device__ __forceinline__ void line_ops_store(LineOps& lo, const LineOps& src) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void line_ops_store(LineOps& lo, const LineOps& src, const int tid) {
+  const int lane = tid & 63;
   const float* s = reinterpret_cast<const float*>(&src);
   float* d = reinterpret_cast<float*>(&lo);
   for (int t = lane; t < kLineOpsFloats; t += 64) d[t] = s[t];
@@ -659,9 +694,10 @@ __device__ __forceinline__ void line_ops_store(LineOps& lo, const LineOps& src) 
 }
 
 // Operator columns of this lane's row for table sign sg and trace side ur.
-__device__ __forceinline__ void line_ops_row(const LineOps& lo, int sg, int ur, float (&dp)[4],
+__device__ __forceinline__ void line_ops_row(const LineOps& lo, int sg, int ur, const int tid,
+                                             float (&dp)[4],
                                              float (&ev)[4]) {
-  const int i = threadIdx.x & 3;
+  const int i = tid & 3;
   const float4 d = *reinterpret_cast<const float4*>(&lo.Dp[sg][i][0]);
   const float4 e = *reinterpret_cast<const float4*>(&lo.E[sg][ur][i][0]);
   dp[0] = d.x, dp[1] = d.y, dp[2] = d.z, dp[3] = d.w;
@@ -690,7 +726,7 @@ __device__ __forceinline__ bool quads_agree(bool pos) {
 template <int DIM, int P, typename CT, bool INC>
 constexpr int stage_waves() {
   return DIM == 3 && P == 3 ? 2
-         : DIM == 3 && P == 2 ? (sizeof(CT) == 8 ? 2 : 3)
+         : DIM == 3 && P == 2 ? (sizeof(CT) == 8 ? 2 : 4)
          : sizeof(CT) == 8 ? 3 : INC ? 4 : 5;
 }
 
@@ -706,12 +742,30 @@ constexpr int stage_waves() {
 // (line_mfma), with the relaxation term formed in FP64 and added to the FP32
 // stage combination in FP64 before the stored value is rounded.
 // ---------------------------------------------------------------------------
-// Work item w (element x velocity chunk, velocity-chunk major) of one stage
-// launch; k_stage runs one item per work-group, k_stage_batch several members'
-// items from a descriptor table.
-template <int DIM, int P, typename ST, int MODE, bool INC = false>
-__device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) {
+// One work item (element e x velocity chunk) of one stage launch; k_stage runs
+// one item per work-group, k_stage_batch one member's item from a descriptor
+// table, k_stage_sweep a column of items along the last axis.
+//
+// Column sweep (SW): the work-group visits the elements of a column in the
+// upwind direction `up` of the last axis (KS = DIM - 1) of its velocity chunk
+// and hands each element's outflow traces on that axis to the next one, so
+// that lanes with sign(u_KS) = up read no neighbour nodes on that axis: the
+// exterior trace of a line is the carried value (`carry`: not the first
+// element of the column). tr holds the carried traces in registers (1-D lines
+// of quadrilaterals, NTR = p + 1 values); hexahedra keep them in LDS (NTR = 1).
+// The carried trace is the same sum, in the same order, as the exterior trace
+// formed from the neighbour's nodes, so the VALU paths give the same bits with
+// and without the sweep.
+template <int DIM, int P>
+constexpr int sweep_tr_regs() {
+  return DIM == 2 ? P + 1 : 1;
+}
+template <int DIM, int P, typename ST, int MODE, bool INC = false, bool SW = false>
+__device__ __forceinline__ void stage_item(const StageArgs& A, const int chunk, const int64_t e,
+                                           const bool count, const bool carry, const bool up,
+                                           typename Compute<ST>::T (&tr)[sweep_tr_regs<DIM, P>()]) {
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
+  static_assert(!SW || (DIM >= 2 && MODE != 1), "column sweeps: quadrilaterals and hexahedra, RK modes");
   using CT = typename Compute<ST>::T;
   // FR line contractions on the matrix cores for FP32 arithmetic on p = 3
   // hexahedra (measured 2-4 % faster there); segments, quadrilaterals and
@@ -724,25 +778,33 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   // when they fit the register budget (1-D and 2-D elements); otherwise each
   // value is read where it is used
   constexpr bool kPreload = NS * DIM <= 48;
+  constexpr int KS = DIM - 1;                 // sweep axis
+  constexpr int NT = ipow(N1, DIM - 1);       // lines along it
+  constexpr bool kTrLds = SW && sweep_tr_regs<DIM, P>() < NT;
   __shared__ double red[(kBlock / 64) * part_rows<NS>() * 5];
   __shared__ FaceRows<CT> frows[kBlock / 64];
   __shared__ LineOps lops[kMfma ? kBlock / 64 : 1];
+  __shared__ CT trl[kTrLds ? NT * kBlock : 1];  // carried traces, [line][lane]
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   double* tab = reinterpret_cast<double*>(dyn_lds);
 
+  // thread index; in a sweep it is opaque to the compiler for every element
+  // of the column, so that what derives from it (the lane's velocity, LDS
+  // addresses) is recomputed per element instead of being held in registers
+  // across the column (which spilled)
+  int tid = (int)threadIdx.x;
+  if constexpr (SW) asm volatile("" : "+v"(tid));
   const DevGeom& g = A.g;
   const DevOpsT<CT>& OP = ops_of<CT>(A);
-  FaceRows<CT>& fr = frows[threadIdx.x >> 6];
-  face_rows_store<CT, N1>(fr, OP);
-  LineOps& lo = lops[kMfma ? threadIdx.x >> 6 : 0];
-  if constexpr (kMfma) line_ops_store(lo, A.lops);
-  const int chunk = (int)(w / A.ecount);
-  const int64_t e = work_element(A.order, A.e0, w, A.ecount);
+  FaceRows<CT>& fr = frows[tid >> 6];
+  face_rows_store<CT, N1>(fr, OP, tid);
+  LineOps& lo = lops[kMfma ? tid >> 6 : 0];
+  if constexpr (kMfma) line_ops_store(lo, A.lops, tid);
   const int64_t nv = g.nv;
   const int S = g.tabw;
   const int64_t node0 = e * NS;
 
-  const int j = chunk * kBlock + (int)threadIdx.x;
+  const int j = chunk * kBlock + tid;
   const bool valid = j < nv;
   const int jj = valid ? j : (int)nv - 1;
   Vel vel = velocity_of(g, jj);
@@ -799,6 +861,17 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
     use_right[k] = (pos[k] != wall);
     src[k] = fin + f_offset(g, src_e, 0, src_j);
   }
+  // sweep: lanes whose upwind neighbour on axis KS is the previous element of
+  // the column take its carried traces; a wave loads that neighbour's nodes
+  // only when one of its lanes does not (uniform)
+  bool lane_carry = false, wave_load = true;
+  if constexpr (SW) {
+    lane_carry = carry && pos[KS] == up;
+    // every wave loads at the column's entry element, also one whose lanes
+    // are all beyond the velocity count: their carried values must be finite
+    // (they enter the moment partials with weight 0)
+    wave_load = !carry || __ballot(valid && !lane_carry) != 0;
+  }
 
   // Global loads in three batches, each issued before any of its values is
   // used: (1) the element's equilibrium rows (factors and 1/tau, first
@@ -814,28 +887,30 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int t = u * kBlock + (int)threadIdx.x;
+      const int t = u * kBlock + tid;
       tv[u] = et[rp.offset(t < rp.count ? t : rp.count - 1)];
     }
   }
-  // BF16-increment stages 2-3: the input is F + increment (same offsets).
-  // F of the own nodes (the f^n of the combine) stays in registers for small
-  // elements and is read again (a cache hit) for hexahedra.
+  // BF16-increment stages: the input of stages 2-3 is F + increment (same
+  // offsets). F of the own nodes (the base of the stored increment, and the
+  // f^n of the combine) stays in registers for small elements and is read
+  // again (a cache hit) for hexahedra.
   constexpr bool kDin = INC && MODE == 0;
-  constexpr bool kKeepF = kDin && NS <= 16;
+  constexpr bool kKeepF = INC && NS <= 16;
   const uint16_t* __restrict__ din = A.din;
   const ST* fe = fin + f_offset(g, e, 0, jj);
   CT f[NS];
   CT fb[kKeepF ? NS : 1];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[i * kVB];
+  if constexpr (kKeepF) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) fb[i] = f[i];
+  }
   if constexpr (kDin) {
     const uint16_t* de = din + (fe - fin);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      if constexpr (kKeepF) fb[i] = f[i];
-      f[i] += bf16_f32(de[i * kVB]);
-    }
+    for (int i = 0; i < NS; ++i) f[i] += bf16_f32(de[i * kVB]);
   }
   CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
   if constexpr (kPreload) {
@@ -851,7 +926,7 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int t = u * kBlock + (int)threadIdx.x;
+      const int t = u * kBlock + tid;
       if (t < rp.count) tab[t] = tv[u];
     }
   }
@@ -865,15 +940,19 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
     int S1 = 1;
 #pragma unroll
     for (int m = 0; m < k; ++m) S1 *= N1;
+    // the neighbour's nodes on this axis are needed (uniform)
+    const bool ld = !SW || k != KS || wave_load;
     if constexpr (kPreload) {
       if (k > 0) {  // batch (2): keep the scheduler from hoisting these loads
         __builtin_amdgcn_sched_barrier(0);
+        if (ld) {
 #pragma unroll
-        for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][i * kVB];
-        if constexpr (kDin) {
-          const uint16_t* ds = din + (src[k] - fin);
+          for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][i * kVB];
+          if constexpr (kDin) {
+            const uint16_t* ds = din + (src[k] - fin);
 #pragma unroll
-          for (int i = 0; i < NS; ++i) nbv[k][i] += bf16_f32(ds[i * kVB]);
+            for (int i = 0; i < NS; ++i) nbv[k][i] += bf16_f32(ds[i * kVB]);
+          }
         }
       }
     }
@@ -887,13 +966,40 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
         return xv;
       }
     };
+    // sweep axis: every lane takes the exterior traces of its lines from the
+    // carried store (tr or trl); where a wave has lanes that do not carry,
+    // those lanes first put there the traces formed from the neighbour's
+    // nodes (the same sums as below without the sweep)
+    if constexpr (SW) {
+      if (k == KS && wave_load) {
+        const CT* re = fr.r[use_right[k] ? 0 : 1];
+        CT lx[N1];
+#pragma unroll
+        for (int bb = 0; bb < N1; ++bb) lx[bb] = re[bb];
+#pragma unroll
+        for (int base = 0; base < NT; ++base) {
+          CT t = (CT)0;
+#pragma unroll
+          for (int bb = 0; bb < N1; ++bb) t += lx[bb] * nbval(base + bb * NT);
+          if constexpr (kTrLds) {
+            if (!lane_carry) trl[base * kBlock + tid] = t;
+          } else {
+            tr[base] = lane_carry ? tr[base] : t;
+          }
+        }
+      }
+    }
+    auto ext_sweep = [&](int base) -> CT {
+      if constexpr (kTrLds) return trl[base * kBlock + tid];
+      else return tr[base];
+    };
     const CT a = (CT)(vel.u[k] * g.scale[k]);
     // diffuse walls of this axis touching the element (uniform)
     const double* rho_lo = nullptr;
     const double* rho_hi = nullptr;
     bool dwall = false;
     CT mw = (CT)0;
-    if constexpr (DIM <= 2) {
+    if constexpr (DIM <= 2 && !SW) {  // sweeps run meshes without diffuse walls
       const int off_lo = sreg(A.wall_off[k][0]), off_hi = sreg(A.wall_off[k][1]);
       const bool dlo = off_lo >= 0 && ek[k] == 0;
       const bool dhi = off_hi >= 0 && ek[k] == sreg(g.nelem[k]) - 1;
@@ -916,25 +1022,37 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
         // applied to the lanes of that sign only
         const bool uni = quads_agree(pos[k]);
         const int npass = uni ? 1 : 2;
+        // sweep axis: the exterior trace t of each line enters as G_in t (one
+        // more 4x4x1 product) instead of E applied to the neighbour's line
         for (int ps = 0; ps < npass; ++ps) {
           const int sg = uni ? (pos[k] ? 1 : 0) : ps;
           const int ur = sg ? (wall_in[k][1] ? 0 : 1) : (wall_in[k][0] ? 1 : 0);
           float dp[4], ev[4];
-          line_ops_row(lo, sg, ur, dp, ev);
+          line_ops_row(lo, sg, ur, tid, dp, ev);
+          const float gin = lo.G[sg][tid & 3];
           const CT as = (uni || (pos[k] ? 1 : 0) == sg) ? a : (CT)0;
 #pragma unroll
           for (int base = 0; base < NS; ++base) {
             if ((base / S1) % N1 != 0) continue;
-            float fl[N1], nl[N1];
+            float fl[N1];
 #pragma unroll
-            for (int bb = 0; bb < N1; ++bb) {
-              fl[bb] = f[base + bb * S1];
-              nl[bb] = nbval(base + bb * S1);
+            for (int bb = 0; bb < N1; ++bb) fl[bb] = f[base + bb * S1];
+            mfma_f4 c;
+            if (SW && k == KS) {
+              c = line_mfma_own<N1>(dp, fl);
+              c = __builtin_amdgcn_mfma_f32_4x4x1f32(gin, ext_sweep(base), c, 0, 0, 0);
+            } else {
+              float nl[N1];
+#pragma unroll
+              for (int bb = 0; bb < N1; ++bb) nl[bb] = nbval(base + bb * S1);
+              c = line_mfma<N1>(dp, ev, fl, nl);
             }
-            const mfma_f4 c = line_mfma<N1>(dp, ev, fl, nl);
 #pragma unroll
             for (int ia = 0; ia < N1; ++ia) acc[base + ia * S1] = fmaf(as, c[ia], acc[base + ia * S1]);
           }
+        }
+        if constexpr (SW) {
+          if (k == KS) sweep_store<N1, NT, kTrLds>(fr.r[up ? 0 : 1], f, trl, tr, tid);
         }
         continue;
       }
@@ -958,9 +1076,12 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
       for (int bb = 0; bb < N1; ++bb) line[bb] = f[base + bb * S1];
       CT own = (CT)0, ext = (CT)0;
 #pragma unroll
-      for (int bb = 0; bb < N1; ++bb) {
-        own += lown[bb] * line[bb];
-        ext += lext[bb] * nbval(base + bb * S1);
+      for (int bb = 0; bb < N1; ++bb) own += lown[bb] * line[bb];
+      if (SW && k == KS) {
+        ext = ext_sweep(base);
+      } else {
+#pragma unroll
+        for (int bb = 0; bb < N1; ++bb) ext += lext[bb] * nbval(base + bb * S1);
       }
       if (dwall) {  // uniform: the element touches a diffuse wall of axis k
         // flux point of this line on the wall face
@@ -977,33 +1098,38 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
         acc[base + ia * S1] += a * df + jump * Gin[ia];
       }
     }
+    if constexpr (SW) {
+      if (k == KS) sweep_store<N1, NT, kTrLds>(fr.r[up ? 0 : 1], f, trl, tr, tid);
+    }
   }
 
-  // f^n: needed only by the final combine, in flight during the relaxation.
-  // f^n and the stage output are streams that no other work-group of the
-  // launch reads again: they are loaded and stored with the non-temporal hint,
-  // so they do not displace from L2 the nodes that the neighbouring
-  // work-groups re-read (3-5 % per launch on the 2-D box and the Taylor-Green
-  // box).
-  CT fnv[NS];
-  if constexpr (kKeepF) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) fnv[i] = fb[i];
-  } else if constexpr (kDin) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) fnv[i] = (CT)fe[i * kVB];
-  } else if constexpr (MODE == 0) {
-    const ST* fn = (const ST*)A.fn + f_offset(g, e, 0, jj);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) fnv[i] = (CT)__builtin_nontemporal_load(&fn[i * kVB]);
-  }
   // BGK relaxation towards the discretely conservative equilibrium (FP64
-  // rows from LDS), combined with the transport and the SSP-RK weights. FP32
-  // arithmetic: f - dt T and the RK weights in FP32, the collision term in
-  // FP64, weighted by b dt and added in FP64, then rounded once. The whole
-  // relaxation sits in the one branch that loads the rows (keeping it there
-  // lets the compiler overlap the LDS reads of all nodes without holding them
-  // across the branch).
+  // rows from LDS), combined with the transport and the SSP-RK weights: the
+  // stage value is a f^n + h with
+  //   h = b (f - dt T) + b dt C,   C = (g - f)/tau in FP64, added in FP64
+  // (FP32 arithmetic: b (f - dt T) in FP32, the sum rounded once). Where it
+  // lowers the register peak (kFold) h is formed before f^n is loaded, so f
+  // and T are dead by then; the matrix-core path of p = 3 hexahedra (whose
+  // peak is in the transport) loads f^n first and rounds a f^n + h once.
+  // The whole relaxation sits in the one branch that loads the rows (keeping
+  // it there lets the compiler overlap the LDS reads of all nodes without
+  // holding them across the branch).
+  constexpr bool kFold = true;
+  // f^n (MODE 0), or the FP32 state F that BF16 increments are taken against
+  // (increment stages). f^n and the stage output are streams that no other
+  // work-group of the launch reads again: they are loaded and stored with
+  // the non-temporal hint, so they do not displace from L2 the nodes that the
+  // neighbouring work-groups re-read (3-5 % per launch on the 2-D box and the
+  // Taylor-Green box). F of the own nodes is kept in registers for small
+  // elements and read again (a cache hit) otherwise.
+  CT fnv[NS];
+  if constexpr (!kFold) {
+    if constexpr (MODE == 0) {
+      const ST* fn = (const ST*)A.fn + f_offset(g, e, 0, jj);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) fnv[i] = (CT)__builtin_nontemporal_load(&fn[i * kVB]);
+    }
+  }
   // positions of this velocity's factors in a node's LDS row (compact)
   const int cx = vel.b[0] - rp.x0, oy = rp.nx + vel.b[1] - rp.y0,
             oz = rp.nxy + vel.b[2] - rp.z0;
@@ -1018,20 +1144,21 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
   if (A.collide) {  // uniform; one branch, so the LDS reads of all nodes overlap
     // rows beyond the first batch (large velocity grids), loaded only now so
     // that their loop does not hold back the waits of the bulk loads
-    table_rest<kU>(tab, et, rp);
+    table_rest<kU>(tab, et, rp, tid);
     lds_barrier();
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       const double c = collision_term(tab + i * rp.ncols, cx, oy, oz, rp.ncols, (double)f[i]);
       if constexpr (MODE == 1) {
         if (valid) oe1[(int64_t)i * nv] = c - (double)acc[i];
-      } else if constexpr (kMfma) {
+      } else if constexpr (!kFold) {
         const CT r = fmaf(-dt, acc[i], f[i]);
         const CT b32 = MODE == 0 ? fmaf(ca, fnv[i], cb * r) : cb * r;
         o[i] = (CT)fma(wc, c, (double)b32);
+      } else if constexpr (sizeof(CT) == 8) {
+        acc[i] = fma(wc, c, cb * (f[i] - dt * acc[i]));
       } else {
-        const CT L = -acc[i] + (CT)c;
-        o[i] = MODE == 0 ? ca * fnv[i] + cb * (f[i] + dt * L) : cb * (f[i] + dt * L);
+        acc[i] = (CT)fma(wc, c, (double)(cb * (f[i] - dt * acc[i])));
       }
     }
   } else {
@@ -1039,15 +1166,34 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
     for (int i = 0; i < NS; ++i) {
       if constexpr (MODE == 1) {
         if (valid) oe1[(int64_t)i * nv] = -(double)acc[i];
+      } else if constexpr (!kFold) {
+        const CT r = fmaf(-dt, acc[i], f[i]);
+        o[i] = MODE == 0 ? fmaf(ca, fnv[i], cb * r) : cb * r;
       } else {
-        const CT L = -acc[i];
-        o[i] = MODE == 0 ? ca * fnv[i] + cb * (f[i] + dt * L) : cb * (f[i] + dt * L);
+        acc[i] = cb * (f[i] - dt * acc[i]);
       }
     }
   }
+  if constexpr (kFold && MODE != 1) {
+    // keep the scheduler from hoisting these loads above the relaxation
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (kKeepF) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) fnv[i] = fb[i];
+    } else if constexpr (INC) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) fnv[i] = (CT)fe[i * kVB];
+    } else if constexpr (MODE == 0) {
+      const ST* fn = (const ST*)A.fn + f_offset(g, e, 0, jj);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) fnv[i] = (CT)__builtin_nontemporal_load(&fn[i * kVB]);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) o[i] = MODE == 0 ? ca * fnv[i] + acc[i] : acc[i];
+  }
 
   if constexpr (MODE == 1) {
-    if (threadIdx.x == 0 && w == 0) atomicAdd(&A.diag[4], 1ull);
+    if (tid == 0 && count) atomicAdd(&A.diag[4], 1ull);
   } else {
     if (A.limiter) {
       CT fmin = o[0];
@@ -1063,7 +1209,7 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
       }
       const unsigned long long nh = __popcll(__ballot(hit));
       const unsigned long long nb = __popcll(__ballot(hit && !(mean > (CT)0)));
-      if ((threadIdx.x & 63) == 0 && nh) {
+      if ((tid & 63) == 0 && nh) {
         atomicAdd(&A.diag[2], nh);
         if (nb) atomicAdd(&A.diag[3], nb);
       }
@@ -1082,9 +1228,8 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
         float omin = INFINITY, smin = INFINITY;  // stage values / stored values
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-          const CT base = MODE == 0 ? fnv[i] : f[i];
           float stored;
-          const uint16_t h = bf16_increment(o[i], base, stored);
+          const uint16_t h = bf16_increment(o[i], fnv[i], stored);
           if (valid) __builtin_nontemporal_store(h, &oe[i * kVB]);
           omin = fminf(omin, o[i]);
           smin = fminf(smin, stored);
@@ -1092,7 +1237,7 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
         }
         // slices whose stored stage is negative where the stage itself is not
         const unsigned long long nviol = __popcll(__ballot(valid && smin < 0.0f && !(omin < 0.0f)));
-        if ((threadIdx.x & 63) == 0 && nviol) atomicAdd(&A.diag[5], nviol);
+        if ((tid & 63) == 0 && nviol) atomicAdd(&A.diag[5], nviol);
       }
     } else {
       ST* out = (ST*)A.out;
@@ -1106,8 +1251,8 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int64_t w) 
     // staging area reuses the equilibrium rows' LDS once every wave is done
     // with them
     if (A.collide) lds_barrier();
-    element_partials_mfma<NS, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, dyn_lds, red);
-    if (threadIdx.x == 0 && w == 0) atomicAdd(&A.diag[4], 1ull);
+    element_partials_mfma<NS, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, dyn_lds, red, tid);
+    if (tid == 0 && count) atomicAdd(&A.diag[4], 1ull);
   }
 }
 
@@ -1115,7 +1260,71 @@ template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
     k_stage(const StageArgs A) {
-  stage_item<DIM, P, ST, MODE, INC>(A, xcd_remap(blockIdx.x, gridDim.x));
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  typename Compute<ST>::T tr[sweep_tr_regs<DIM, P>()];
+  stage_item<DIM, P, ST, MODE, INC>(A, (int)(w / A.ecount), work_element(A.order, A.e0, w, A.ecount),
+                                    w == 0, false, false, tr);
+}
+
+// Pointer into argument memory that is read-only while kernels run (kernel
+// arguments, descriptor tables): loads through the constant address space
+// become scalar loads that the compiler may repeat where a value is used,
+// instead of vector loads (or scalar registers) held across a loop.
+template <typename T>
+using table_ptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ const T& table_entry(table_ptr<T> p, int64_t i) {
+  return *(const T*)&p[i];
+}
+
+// Direction of the column sweep of velocity chunk `chunk` (slots from v0 on):
+// true when the last transported component of its first velocity slot is
+// positive (the test the stage kernels make per lane), i.e. when the sweep
+// runs towards increasing element index on the last axis. Lanes of the chunk
+// with the other sign read their neighbours as in k_stage.
+__device__ __forceinline__ bool sweep_up(const DevGeom& g, int v0) {
+  int b[3];
+  slot_nodes(g, v0 < g.nv ? v0 : (int)g.nv - 1, b);
+  const int k = g.dim - 1;
+  return (g.vlo[k] + b[k] * g.du[k]) * g.scale[k] > 0.0;
+}
+
+// Stage launch as column sweeps (RK stages over the whole mesh; no diffuse
+// wall on the last axis). Work item w = (velocity chunk, segment of sweep_seg
+// elements of one column along the last axis); columns vary fastest, so the
+// work-groups in flight on an XCD hold neighbouring columns at about the same
+// position along the sweep, and their x (and y) neighbours' nodes are read
+// while still in L2. Each work-group walks its segment in the upwind
+// direction of its chunk, carrying the outflow traces (stage_item).
+template <int DIM, int P, typename ST, int MODE, bool INC = false>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
+    k_stage_sweep(const StageArgs A) {
+  const DevGeom& g = A.g;
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int nl = sreg(g.nelem[DIM - 1]), seg = sreg(A.sweep_seg);
+  const int64_t ncol = g.ne / nl, nseg = nl / seg, per_chunk = ncol * nseg;
+  const int chunk = (int)(w / per_chunk);
+  const int64_t r = w - (int64_t)chunk * per_chunk;
+  const int64_t sg = r / ncol, col = r - sg * ncol;
+  const bool up = sweep_up(g, chunk * kBlock);
+  typename Compute<ST>::T tr[sweep_tr_regs<DIM, P>()];
+  // the arguments are read through a pointer the compiler cannot follow
+  // across iterations, so that they are fetched again (scalar loads) where an
+  // element needs them instead of being held in scalar registers across the
+  // column (which spilled)
+  table_ptr<StageArgs> ap = (table_ptr<StageArgs>)__builtin_amdgcn_kernarg_segment_ptr();
+  for (int s = 0; s < seg; ++s) {
+    const int el = (int)(sg * seg) + s;
+    const int64_t e = col + (int64_t)(up ? el : nl - 1 - el) * ncol;
+    // the previous item's last LDS reads (partial sums) are ordered before
+    // this item's writes by the barrier of the relaxation; without collisions
+    // by this one
+    if (s > 0 && !A.collide) lds_barrier();
+    asm volatile("" : "+s"(ap));
+    stage_item<DIM, P, ST, MODE, INC, true>(table_entry(ap, 0), chunk, e, w == 0 && s == 0, s > 0,
+                                            up, tr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,17 +1337,8 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 constexpr int kMaxBatchMembers = 64;
 
-// Pointer into a descriptor table. The tables are rewritten by copies between
-// launches and never during one, so kernels read them through the constant
-// address space: uniform loads from it become scalar loads that the compiler
-// may repeat where a value is used, instead of vector loads whose results
-// would stay live in vector registers across the work loop.
-template <typename T>
-using table_ptr = const __attribute__((address_space(4))) T*;
-template <typename T>
-__device__ __forceinline__ const T& table_entry(table_ptr<T> p, int64_t i) {
-  return *(const T*)&p[i];
-}
+// The tables are rewritten by copies between launches and never during one,
+// so kernels read them through table_ptr (constant address space).
 struct BatchList {
   int32_t n;     // members covered
   int32_t pad;
@@ -1178,8 +1378,11 @@ __global__ void __launch_bounds__(kBlock)
   // one item per work-group; the grid is the list's item count
   const int32_t u = (int32_t)xcd_remap(blockIdx.x, gridDim.x);
   const int m = batch_member(list->stage_off, list->n, u);
-  stage_item<DIM, P, ST, MODE>(table_entry(args, list->slot[m] * 3 + stage),
-                               u - list->stage_off[m]);
+  const StageArgs& A = table_entry(args, list->slot[m] * 3 + stage);
+  const int64_t w = u - list->stage_off[m];
+  typename Compute<ST>::T tr[sweep_tr_regs<DIM, P>()];
+  stage_item<DIM, P, ST, MODE>(A, (int)(w / A.ecount), work_element(A.order, A.e0, w, A.ecount),
+                               w == 0, false, false, tr);
 }
 
 // Moment partials of a stored state (first stage after installation).
@@ -1204,7 +1407,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(const StageArgs A) {
   CT f[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) f[i] = (CT)fe[i * kVB];
-  element_partials_mfma<NS, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, dyn_lds, red);
+  element_partials_mfma<NS, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, dyn_lds, red,
+                                    (int)threadIdx.x);
 }
 
 }  // namespace bgk

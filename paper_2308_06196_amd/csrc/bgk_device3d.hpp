@@ -63,12 +63,13 @@ template <int P, typename ST, typename CT>
 __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2], const Vel& vel,
                                                     double* __restrict__ partials, int64_t node0,
                                                     int64_t nx, int chunk, int lp,
-                                                    unsigned char* stage, double* red) {
+                                                    unsigned char* stage, double* red,
+                                                    const int tid) {
   using PL = Plane3<P>;
   constexpr int N1 = PL::N1, G = PL::G, P2 = PL::P2, NS = PL::NS;
   constexpr int K = 64 / G, RS = K + 2;
   static_assert(P2 <= 16, "the nodes of a plane fill at most one 16-row tile");
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int vw = lane / G;  // velocity of this lane inside the wave
   double* ps = reinterpret_cast<double*>(stage) + wave * K * 5;
   ST* gw = reinterpret_cast<ST*>(stage + (kBlock / 64) * K * 5 * sizeof(double)) +
@@ -88,9 +89,9 @@ __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  wave_moments_4x4<N1, P2, K, ST>(gw, RS, ps, red + wave * NS * 5);
+  wave_moments_4x4<N1, P2, K, ST>(gw, RS, ps, red + wave * NS * 5, tid);
   lds_barrier();
-  for (int t = threadIdx.x; t < NS * 5; t += kBlock) {
+  for (int t = tid; t < NS * 5; t += kBlock) {
     const int node = t / 5, m = t - node * 5;
     double sum = red[node * 5 + m];
 #pragma unroll
@@ -100,11 +101,29 @@ __device__ __forceinline__ void plane_partials_mfma(const CT (&fv)[Plane3<P>::P2
 }
 
 
-template <int P, typename ST, int MODE, bool INC = false>
-__global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 2 : 3)))
-    k_stage3(const StageArgs A) {
+// One work item (element e x velocity chunk) of the plane-split stage. With
+// SW (column sweep along z, see stage_item) the group's z-outflow traces are
+// carried from the previous element of the column in LDS (one value per
+// velocity and z-line, written by the group's first lane).
+// The (p+1)^2 values of one plane of a neighbour (BF16-increment stages:
+// F + increment).
+template <int P2, bool DIN, typename CT, typename ST>
+__device__ __forceinline__ void load_planes(CT (&v)[P2], const ST* src, const ST* fin,
+                                            const uint16_t* din) {
+#pragma unroll
+  for (int q = 0; q < P2; ++q) v[q] = (CT)src[q * kVB];
+  if constexpr (DIN) {
+    const uint16_t* ds = din + (src - fin);
+#pragma unroll
+    for (int q = 0; q < P2; ++q) v[q] += bf16_f32(ds[q * kVB]);
+  }
+}
+
+template <int P, typename ST, int MODE, bool INC = false, bool SW = false>
+__device__ __forceinline__ void stage3_item(const StageArgs& A, const int chunk, const int64_t e,
+                                            const bool count, const bool carry, const bool up) {
   static_assert(!INC || (MODE != 1 && sizeof(ST) == 4), "increment stages: FP32 state, RK modes");
+  static_assert(!SW || MODE != 1, "column sweeps: RK modes");
   using CT = typename Compute<ST>::T;
   using PL = Plane3<P>;
   constexpr bool kMfma = sizeof(CT) == 4;
@@ -112,26 +131,27 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ double red[(kBlock / 64) * NS * 5];
   __shared__ FaceRows<CT> frows[kBlock / 64];
   __shared__ LineOps lops[kMfma ? kBlock / 64 : 1];
+  __shared__ CT trl[SW ? P2 * VB : 1];  // carried z-traces, [line][velocity of the work-group]
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   double* tab = reinterpret_cast<double*>(dyn_lds);
 
+  // thread index, opaque per element in a sweep (see stage_item)
+  int tid = (int)threadIdx.x;
+  if constexpr (SW) asm volatile("" : "+v"(tid));
   const DevGeom& g = A.g;
   const DevOpsT<CT>& OP = ops_of<CT>(A);
-  FaceRows<CT>& fr = frows[threadIdx.x >> 6];
-  face_rows_store<CT, N1, true>(fr, OP);
-  LineOps& lo = lops[kMfma ? threadIdx.x >> 6 : 0];
-  if constexpr (kMfma) line_ops_store(lo, A.lops);
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
-  const int chunk = (int)(w / A.ecount);
-  const int64_t e = work_element(A.order, A.e0, w, A.ecount);
+  FaceRows<CT>& fr = frows[tid >> 6];
+  face_rows_store<CT, N1, true>(fr, OP, tid);
+  LineOps& lo = lops[kMfma ? tid >> 6 : 0];
+  if constexpr (kMfma) line_ops_store(lo, A.lops, tid);
   const int64_t nv = g.nv;
   const int S = g.tabw;
   const int64_t node0 = e * NS;
 
-  const int lp = (int)threadIdx.x % G;           // plane owned by this lane
+  const int lp = tid % G;                        // plane owned by this lane
   const bool live = lp < N1;
   const int pl = live ? lp : N1 - 1;             // address plane (idle lanes)
-  const int j = chunk * VB + (int)threadIdx.x / G;
+  const int j = chunk * VB + tid / G;
   const bool valid = j < nv;
   const bool act = valid && live;
   const int jj = valid ? j : (int)nv - 1;
@@ -177,6 +197,17 @@ __global__ void __launch_bounds__(kBlock)
     use_right[k] = (pos[k] != wall);
     src[k] = fin + f_offset(g, src_e, pl * P2, src_j);
   }
+  // sweep: groups whose upwind z-neighbour is the previous element of the
+  // column take its carried traces; a wave loads the z-neighbour's planes only
+  // when one of its groups does not (uniform)
+  bool lane_carry = false, wave_load = true;
+  if constexpr (SW) {
+    lane_carry = carry && pos[2] == up;
+    // every wave loads at the column's entry element, also one whose lanes
+    // are all beyond the velocity count: their carried values must be finite
+    // (they enter the moment partials with weight 0)
+    wave_load = !carry || __ballot(valid && !lane_carry) != 0;
+  }
 
   // loads: equilibrium rows (first batch), own plane, the x-, y- and
   // z-neighbours' planes, f^n plane
@@ -190,7 +221,7 @@ __global__ void __launch_bounds__(kBlock)
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {  // clamped, unconditional loads
-      const int t = u * kBlock + (int)threadIdx.x;
+      const int t = u * kBlock + tid;
       tv[u] = et[rp.offset(t < rp.count ? t : rp.count - 1)];
     }
   }
@@ -201,35 +232,40 @@ __global__ void __launch_bounds__(kBlock)
   CT f[P2];
 #pragma unroll
   for (int q = 0; q < P2; ++q) f[q] = (CT)fe[q * kVB];
-  CT nb[3][P2];
+  // sweep: the z-neighbour's planes are not held (see the z part). FP64
+  // arithmetic loads the neighbours' planes one axis at a time (the next
+  // axis' after this axis' transport), so that no more than one neighbour's
+  // planes are held at once; FP32 arithmetic loads them all in the first
+  // batch.
+  constexpr int NB = SW ? 2 : 3;
+  constexpr bool kStaged = sizeof(CT) == 8;
+  CT nb[NB][P2];
+  if constexpr (kStaged) {
+    load_planes<P2, kDin>(nb[0], src[0], fin, din);
+  } else {
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < NB; ++k)
 #pragma unroll
-    for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][q * kVB];
-  CT fnv[P2];  // needed only by the final combine (F of the own nodes for increments)
+      for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][q * kVB];
+  }
   if constexpr (kDin) {
     const uint16_t* de = din + (fe - fin);
 #pragma unroll
-    for (int q = 0; q < P2; ++q) {
-      fnv[q] = f[q];
-      f[q] += bf16_f32(de[q * kVB]);
+    for (int q = 0; q < P2; ++q) f[q] += bf16_f32(de[q * kVB]);
+    if constexpr (!kStaged) {
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const uint16_t* ds = din + (src[k] - fin);
+#pragma unroll
+        for (int q = 0; q < P2; ++q) nb[k][q] += bf16_f32(ds[q * kVB]);
+      }
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint16_t* ds = din + (src[k] - fin);
-#pragma unroll
-      for (int q = 0; q < P2; ++q) nb[k][q] += bf16_f32(ds[q * kVB]);
-    }
-  } else if constexpr (MODE == 0) {
-    const ST* fn = (const ST*)A.fn + f_offset(g, e, pl * P2, jj);
-#pragma unroll
-    for (int q = 0; q < P2; ++q) fnv[q] = (CT)__builtin_nontemporal_load(&fn[q * kVB]);  // streams: see k_stage
   }
 
   if (A.collide) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int t = u * kBlock + (int)threadIdx.x;
+      const int t = u * kBlock + tid;
       if (t < rp.count) tab[t] = tv[u];
     }
   }
@@ -243,6 +279,10 @@ __global__ void __launch_bounds__(kBlock)
   // p >= 2, two velocities for p = 1)
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
+    if (kStaged && k > 0) {  // keep the scheduler from hoisting these loads
+      __builtin_amdgcn_sched_barrier(0);
+      load_planes<P2, kDin>(nb[k], src[k], fin, din);
+    }
     const int S1 = k == 0 ? 1 : N1;
     const CT a = (CT)(vel.u[k] * g.scale[k]);
     if constexpr (kMfma) {
@@ -252,7 +292,7 @@ __global__ void __launch_bounds__(kBlock)
         const int sg = uni ? (pos[k] ? 1 : 0) : ps;
         const int ur = sg ? (wall_in[k][1] ? 0 : 1) : (wall_in[k][0] ? 1 : 0);
         float dp[4], ev[4];
-        line_ops_row(lo, sg, ur, dp, ev);
+        line_ops_row(lo, sg, ur, tid, dp, ev);
         const CT as = (uni || (pos[k] ? 1 : 0) == sg) ? a : (CT)0;
 #pragma unroll
         for (int base = 0; base < P2; ++base) {
@@ -303,6 +343,10 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   }
+  if constexpr (kStaged && !SW) {
+    __builtin_amdgcn_sched_barrier(0);
+    load_planes<P2, kDin>(nb[NB - 1], src[2], fin, din);
+  }
   // z: the column of node q is spread over the group's lanes; lane lp holds
   // plane lp and its partners lane ^ r the other planes. The derivative is
   // sum_r D[lp][lp ^ r] f(lp ^ r); the trace difference ext - own is one
@@ -313,7 +357,23 @@ __global__ void __launch_bounds__(kBlock)
     const CT* re = fr.r[use_right[2] ? 0 : 1];
     const CT lown_mine = live ? ro[pl] : (CT)0;
     const CT lext_mine = live ? re[pl] : (CT)0;
+    const CT lout_mine = live ? fr.r[up ? 0 : 1][pl] : (CT)0;  // sweep: outflow trace weight
+    const int vg = tid / G;                                 // velocity inside the work-group
     const CT ag = a * ro[kMaxN1 + pl];
+    // sweep: every group takes its z-exterior traces from trl; where a wave
+    // has groups that do not carry, those groups first put there the traces
+    // formed from the z-neighbour's planes
+    if constexpr (SW) {
+      if (wave_load) {
+#pragma unroll
+        for (int q = 0; q < P2; ++q) {
+          CT v = (CT)src[2][q * kVB];
+          if constexpr (kDin) v += bf16_f32(din[(src[2] - fin) + q * kVB]);
+          const CT t = group_allsum<G>(lext_mine * v);
+          if (!lane_carry) trl[q * VB + vg] = t;
+        }
+      }
+    }
     CT Dr[G];
 #pragma unroll
     for (int r = 0; r < G; ++r) {
@@ -329,14 +389,22 @@ __global__ void __launch_bounds__(kBlock)
         df += Dr[2] * quad_xor<2>(fq);
         df += Dr[3] * quad_xor<3>(fq);
       }
-      const CT jl = group_allsum<G>(lext_mine * nb[2][q] - lown_mine * fq);
+      CT jl;
+      if constexpr (SW) {
+        jl = trl[q * VB + vg] - group_allsum<G>(lown_mine * fq);
+        // outflow trace of this line for the next element of the column
+        // (every lane of the group writes the same value)
+        trl[q * VB + vg] = group_allsum<G>(lout_mine * fq);
+      } else {
+        jl = group_allsum<G>(lext_mine * nb[NB - 1][q] - lown_mine * fq);
+      }
       acc[q] += a * df + ag * jl;
     }
   }
 
-  // relaxation and RK combination (as in k_stage: the collision term in
-  // FP64 from the FP64 rows; FP32 arithmetic adds it to the FP32 combination
-  // in FP64), all inside the branch that loads the rows
+  // relaxation folded with the transport into h = b (f - dt T) + b dt C
+  // before f^n is loaded (as in stage_item: C in FP64 from the FP64 rows,
+  // added in FP64), all inside the branch that loads the rows
   // positions of this velocity's factors in a node's LDS row (compact)
   const int cx = vel.b[0] - rp.x0, oy = rp.nx + vel.b[1] - rp.y0,
             oz = rp.nxy + vel.b[2] - rp.z0;
@@ -348,22 +416,18 @@ __global__ void __launch_bounds__(kBlock)
   }
   const CT dt = (CT)A.dt, ca = (CT)A.a, cb = (CT)A.b;
   const double wc = A.b * A.dt;
-  CT o[P2];
   if (A.collide) {  // uniform: rows beyond the first batch, then the relaxation
-    table_rest<kU>(tab, et, rp);
+    table_rest<kU>(tab, et, rp, tid);
     lds_barrier();
 #pragma unroll
     for (int q = 0; q < P2; ++q) {
       const double c = collision_term(tp + q * rp.ncols, cx, oy, oz, rp.ncols, (double)f[q]);
       if constexpr (MODE == 1) {
         if (act) oe1[(int64_t)q * nv] = c - (double)acc[q];
-      } else if constexpr (kMfma) {
-        const CT r = fmaf(-dt, acc[q], f[q]);
-        const CT b32 = MODE == 0 ? fmaf(ca, fnv[q], cb * r) : cb * r;
-        o[q] = (CT)fma(wc, c, (double)b32);
+      } else if constexpr (sizeof(CT) == 8) {  // h, kept in acc
+        acc[q] = fma(wc, c, cb * (f[q] - dt * acc[q]));
       } else {
-        const CT L = -acc[q] + (CT)c;
-        o[q] = MODE == 0 ? ca * fnv[q] + cb * (f[q] + dt * L) : cb * (f[q] + dt * L);
+        acc[q] = (CT)fma(wc, c, (double)(cb * (f[q] - dt * acc[q])));
       }
     }
   } else {
@@ -372,14 +436,31 @@ __global__ void __launch_bounds__(kBlock)
       if constexpr (MODE == 1) {
         if (act) oe1[(int64_t)q * nv] = -(double)acc[q];
       } else {
-        const CT L = -acc[q];
-        o[q] = MODE == 0 ? ca * fnv[q] + cb * (f[q] + dt * L) : cb * (f[q] + dt * L);
+        acc[q] = cb * (f[q] - dt * acc[q]);
       }
     }
   }
+  // f^n (MODE 0; a stream, see stage_item), or F of the own nodes, the base
+  // of the BF16 increments (read again: a cache hit)
+  CT fnv[P2];
+  // keep the scheduler from hoisting these loads above the relaxation
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (INC) {
+#pragma unroll
+    for (int q = 0; q < P2; ++q) fnv[q] = (CT)fe[q * kVB];
+  } else if constexpr (MODE == 0) {
+    const ST* fn = (const ST*)A.fn + f_offset(g, e, pl * P2, jj);
+#pragma unroll
+    for (int q = 0; q < P2; ++q) fnv[q] = (CT)__builtin_nontemporal_load(&fn[q * kVB]);
+  }
+  CT o[P2];
+  if constexpr (MODE != 1) {
+#pragma unroll
+    for (int q = 0; q < P2; ++q) o[q] = MODE == 0 ? ca * fnv[q] + acc[q] : acc[q];
+  }
 
   if constexpr (MODE == 1) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
+    if (tid == 0 && count) atomicAdd(&A.diag[4], 1ull);
   } else {
     if (A.limiter) {
       // element mean and minimum over all planes of the velocity
@@ -405,7 +486,7 @@ __global__ void __launch_bounds__(kBlock)
       }
       const unsigned long long nh = __popcll(__ballot(hit && lp == 0));
       const unsigned long long nb2 = __popcll(__ballot(hit && lp == 0 && !(mean > (CT)0)));
-      if ((threadIdx.x & 63) == 0 && nh) {
+      if ((tid & 63) == 0 && nh) {
         atomicAdd(&A.diag[2], nh);
         if (nb2) atomicAdd(&A.diag[3], nb2);
       }
@@ -424,9 +505,8 @@ __global__ void __launch_bounds__(kBlock)
         float omin = INFINITY, smin = INFINITY;  // stage values / stored values
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
-          const CT base = MODE == 0 ? fnv[q] : f[q];
           float stored;
-          const uint16_t h = bf16_increment(o[q], base, stored);
+          const uint16_t h = bf16_increment(o[q], fnv[q], stored);
           if (act) __builtin_nontemporal_store(h, &oe[q * kVB]);
           omin = fminf(omin, o[q]);
           smin = fminf(smin, stored);
@@ -435,7 +515,7 @@ __global__ void __launch_bounds__(kBlock)
         // (velocity, plane) pairs whose stored stage is negative where the
         // stage itself is not
         const unsigned long long nviol = __popcll(__ballot(act && smin < 0.0f && !(omin < 0.0f)));
-        if ((threadIdx.x & 63) == 0 && nviol) atomicAdd(&A.diag[5], nviol);
+        if ((tid & 63) == 0 && nviol) atomicAdd(&A.diag[5], nviol);
       }
     } else if (act) {
       ST* oe = (ST*)A.out + f_offset(g, e, pl * P2, j);
@@ -445,8 +525,42 @@ __global__ void __launch_bounds__(kBlock)
     // moment partials on the matrix cores; the staging area reuses the
     // equilibrium rows' LDS once every wave is done with them
     if (A.collide) lds_barrier();
-    plane_partials_mfma<P, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, lp, dyn_lds, red);
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&A.diag[4], 1ull);
+    plane_partials_mfma<P, ST, CT>(o, vel, A.partials, node0, g.nx, chunk, lp, dyn_lds, red, tid);
+    if (tid == 0 && count) atomicAdd(&A.diag[4], 1ull);
+  }
+}
+
+// Three waves per SIMD (FP64: the neighbours' planes loaded one axis at a
+// time fit 168 registers).
+template <int P, typename ST, int MODE, bool INC = false>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+    k_stage3(const StageArgs A) {
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  stage3_item<P, ST, MODE, INC>(A, (int)(w / A.ecount), work_element(A.order, A.e0, w, A.ecount),
+                                w == 0, false, false);
+}
+
+// Plane-split stage as column sweeps along z (see k_stage_sweep).
+template <int P, typename ST, int MODE, bool INC = false>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 2 : 3)))
+    k_stage3_sweep(const StageArgs A) {
+  const DevGeom& g = A.g;
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int nl = sreg(g.nelem[2]), seg = sreg(A.sweep_seg);
+  const int64_t ncol = g.ne / nl, nseg = nl / seg, per_chunk = ncol * nseg;
+  const int chunk = (int)(w / per_chunk);
+  const int64_t r = w - (int64_t)chunk * per_chunk;
+  const int64_t sg = r / ncol, col = r - sg * ncol;
+  const bool up = sweep_up(g, chunk * Plane3<P>::VB);
+  // arguments re-read per element (see k_stage_sweep)
+  table_ptr<StageArgs> ap = (table_ptr<StageArgs>)__builtin_amdgcn_kernarg_segment_ptr();
+  for (int s = 0; s < seg; ++s) {
+    const int el = (int)(sg * seg) + s;
+    const int64_t e = col + (int64_t)(up ? el : nl - 1 - el) * ncol;
+    if (s > 0 && !A.collide) lds_barrier();
+    asm volatile("" : "+s"(ap));
+    stage3_item<P, ST, MODE, INC, true>(table_entry(ap, 0), chunk, e, w == 0 && s == 0, s > 0, up);
   }
 }
 
@@ -474,7 +588,8 @@ __global__ void __launch_bounds__(kBlock) k_moments3(const StageArgs A) {
   CT f[P2];
 #pragma unroll
   for (int q = 0; q < P2; ++q) f[q] = (CT)fe[q * kVB];
-  plane_partials_mfma<P, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, lp, dyn_lds, red);
+  plane_partials_mfma<P, ST, CT>(f, vel, A.partials, e * NS, g.nx, chunk, lp, dyn_lds, red,
+                                 (int)threadIdx.x);
 }
 
 }  // namespace bgk

@@ -4,6 +4,9 @@
 // partials), the residual, stand-alone moment partials, the per-node Newton
 // solve for the discretely conservative equilibrium, and state conversion /
 // Maxwellian initialisation. All launched on the caller's stream.
+#include <cmath>
+#include <cstdlib>
+
 #include "bgk_device.hpp"
 #include "bgk_device3d.hpp"
 #include "bgk_launch.hpp"
@@ -521,13 +524,67 @@ constexpr bool kHexOneLane(bool inc) {
   return sizeof(ST) == 8 ? P <= 2 : (P <= 2 || !inc);
 }
 
+// RK stages over the whole mesh run as column sweeps along the last axis
+// (k_stage_sweep, k_stage3_sweep) when the solver chose a segment length and
+// the mesh has no diffuse wall.
+static bool use_sweep(int mode, const StageArgs& A) {
+  if (mode != 0 || A.sweep_seg <= 0 || A.g.dim < 2) return false;
+  if (A.e0 != 0 || A.ecount != A.g.ne || A.g.nelem[A.g.dim - 1] % A.sweep_seg != 0) return false;
+  for (int k = 0; k < 2; ++k)
+    if (A.wall_off[k][0] >= 0 || A.wall_off[k][1] >= 0) return false;
+  return true;
+}
+
+static dim3 sweep_grid(const StageArgs& A) {
+  return dim3((unsigned)(A.g.nchunk * (A.g.ne / A.sweep_seg)));
+}
+
+template <int D, int P, typename ST, bool kIncBuilt = true>
+static void launch_sweep(bool inc, const StageArgs& A, size_t lds, hipStream_t s) {
+  const dim3 grid = sweep_grid(A), block(kBlock);
+  if constexpr (sizeof(ST) == 4 && kIncBuilt) {
+    if (inc) {
+      if (A.din)
+        hipLaunchKernelGGL((k_stage_sweep<D, P, ST, 0, true>), grid, block, lds, s, A);
+      else
+        hipLaunchKernelGGL((k_stage_sweep<D, P, ST, 3, true>), grid, block, lds, s, A);
+      return;
+    }
+  }
+  if (A.a != 0.0)
+    hipLaunchKernelGGL((k_stage_sweep<D, P, ST, 0>), grid, block, lds, s, A);
+  else
+    hipLaunchKernelGGL((k_stage_sweep<D, P, ST, 3>), grid, block, lds, s, A);
+}
+
+template <int P, typename ST>
+static void launch_sweep3(bool inc, const StageArgs& A, size_t lds, hipStream_t s) {
+  const dim3 grid = sweep_grid(A), block(kBlock);
+  if constexpr (sizeof(ST) == 4) {
+    if (inc) {
+      if (A.din)
+        hipLaunchKernelGGL((k_stage3_sweep<P, ST, 0, true>), grid, block, lds, s, A);
+      else
+        hipLaunchKernelGGL((k_stage3_sweep<P, ST, 3, true>), grid, block, lds, s, A);
+      return;
+    }
+  }
+  if (A.a != 0.0)
+    hipLaunchKernelGGL((k_stage3_sweep<P, ST, 0>), grid, block, lds, s, A);
+  else
+    hipLaunchKernelGGL((k_stage3_sweep<P, ST, 3>), grid, block, lds, s, A);
+}
+
 template <int P, typename ST>
 static hipError_t hex_dispatch(int mode, bool inc, const StageArgs& A, size_t tab, size_t lds,
                                dim3 grid, dim3 block, hipStream_t s) {
+  const bool sweep = use_sweep(mode, A);
   if (kHexOneLane<P, ST>(inc)) {
     if constexpr (sizeof(ST) == 8 && P > 2) return hipErrorInvalidValue;  // not built
     else {
-      if (mode == 0 && inc) {
+      if (sweep) {
+        launch_sweep<3, P, ST, (P <= 2)>(inc, A, lds, s);  // one-lane increments: p <= 2
+      } else if (mode == 0 && inc) {
         if constexpr (sizeof(ST) == 4 && P <= 2) {
           if (A.din)
             hipLaunchKernelGGL((k_stage<3, P, ST, 0, true>), grid, block, lds, s, A);
@@ -549,7 +606,9 @@ static hipError_t hex_dispatch(int mode, bool inc, const StageArgs& A, size_t ta
   // plane-split; the FP64 ones decode lexicographic slots (one octant)
   if (sizeof(ST) == 8 && A.g.voct[7] != 0) return hipErrorInvalidValue;
   const size_t lds3 = mode != 1 ? std::max(tab, (size_t)mfma3_lds_bytes<P, ST>()) : tab;
-  if (mode == 0 && inc) {
+  if (sweep) {
+    launch_sweep3<P, ST>(inc, A, lds3, s);
+  } else if (mode == 0 && inc) {
     if constexpr (sizeof(ST) == 4) {
       if (A.din)
         hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3, s, A);
@@ -578,6 +637,10 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
   const size_t lds = mode != 1 ? std::max(tab, (size_t)mfma_lds_bytes<ST>()) : tab;
 #define BGK_CASE(D, P)                                                     \
   case D * 10 + P:                                                         \
+    if (D >= 2 && use_sweep(mode, A)) {                                    \
+      launch_sweep<(D >= 2 ? D : 2), P, ST>(inc, A, lds, s);               \
+      break;                                                               \
+    }                                                                      \
     if constexpr (sizeof(ST) == 4) {                                       \
       if (mode == 0 && inc) {                                              \
         if (A.din)                                                         \
@@ -609,6 +672,106 @@ static hipError_t stage_dispatch(int mode, bool inc, const StageArgs& A, hipStre
 #undef BGK_CASE
 #undef BGK_CASE3
   return hipGetLastError();
+}
+
+// Work-groups of kernel k (256 lanes, lds bytes of dynamic LDS) that one CU
+// holds at once.
+template <typename K>
+static int groups_per_cu(K k, size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kBlock, lds) != hipSuccess) return 0;
+  return n;
+}
+
+template <int D, int P, typename ST>
+static int sweep_groups_per_cu(bool inc, size_t tab) {
+  if constexpr (D == 3) {
+    if (!kHexOneLane<P, ST>(inc)) {
+      const size_t lds = std::max(tab, (size_t)mfma3_lds_bytes<P, ST>());
+      if constexpr (sizeof(ST) == 4) {
+        if (inc) return groups_per_cu(k_stage3_sweep<P, ST, 0, true>, lds);
+      }
+      return groups_per_cu(k_stage3_sweep<P, ST, 0>, lds);
+    }
+    if constexpr (sizeof(ST) == 8 && P > 2) return 0;  // not built
+  }
+  const size_t lds = std::max(tab, (size_t)mfma_lds_bytes<ST>());
+  if constexpr (sizeof(ST) == 4 && (D == 2 || P <= 2)) {
+    if (inc) return groups_per_cu(k_stage_sweep<D, P, ST, 0, true>, lds);
+  }
+  if constexpr (sizeof(ST) == 8 && D == 3 && P > 2) return 0;
+  else return groups_per_cu(k_stage_sweep<D, P, ST, 0>, lds);
+}
+
+template <typename ST>
+static int sweep_groups(int dim, int order, bool inc, size_t tab) {
+  switch (dim * 10 + order) {
+    case 21: return sweep_groups_per_cu<2, 1, ST>(inc, tab);
+    case 22: return sweep_groups_per_cu<2, 2, ST>(inc, tab);
+    case 23: return sweep_groups_per_cu<2, 3, ST>(inc, tab);
+    case 31: return sweep_groups_per_cu<3, 1, ST>(inc, tab);
+    case 32: return sweep_groups_per_cu<3, 2, ST>(inc, tab);
+    case 33: return sweep_groups_per_cu<3, 3, ST>(inc, tab);
+    default: return 0;
+  }
+}
+
+// Elements per column-sweep work item (0: no sweep). A work-group walks its
+// segment one element after another, so long segments leave the last wave
+// of work-groups part of the device idle; each segment's first element reads
+// its upwind neighbour's nodes. The choice minimises (1 + 0.2 / seg) / eff,
+// eff = R / ceil(R) for R = work items / work-groups resident on the device
+// (from the kernel's occupancy), over the divisors seg >= 2 of the number of
+// elements along the last axis; seg = 1 (no sweep) when that is cheaper.
+// The environment variable BGK_SWEEP_SEG overrides the choice (0: no sweep;
+// a length that does not divide the column length means no sweep).
+// Sweeps are used where they measured faster than the per-element kernels
+// (ms per stage launch, sweep / per element): quadrilaterals in FP64 (32^2
+// box, p = 3: 1.021 / 1.039), p = 3 hexahedra in FP32 (Taylor-Green box,
+// one lane per velocity: 3.46 / 3.50) and with BF16 increments (plane-split:
+// 6.34 / 6.46). Not for FP32 and BF16 quadrilaterals (0.626 / 0.588, the
+// loop costs registers at five waves per SIMD), p = 2 hexahedra (Mach-2 box
+// at four waves per SIMD: spills) or FP64 p = 3 hexahedra (the plane-split
+// sweep needs two waves per SIMD where the per-element kernel runs three:
+// 10.2 / 9.88).
+static bool sweep_pays(const DevGeom& g, int precision) {
+  if (g.dim == 2) return precision == 0;
+  return g.dim == 3 && g.n1 == 4 && precision != 0;
+}
+
+int sweep_segment(const DevGeom& g, int precision, bool collide) {
+  if (g.dim < 2) return 0;
+  const int nl = g.nelem[g.dim - 1];
+  if (const char* env = getenv("BGK_SWEEP_SEG")) {
+    const int v = atoi(env);
+    return v >= 1 && nl % v == 0 ? v : 0;
+  }
+  if (!sweep_pays(g, precision)) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const size_t tab = collide ? (size_t)g.ns * g.tabw * sizeof(double) : 0;
+  const bool inc = precision == 2;
+  const int per_cu = precision == 0 ? sweep_groups<double>(g.dim, g.n1 - 1, false, tab)
+                                    : sweep_groups<float>(g.dim, g.n1 - 1, inc, tab);
+  (void)hipGetLastError();
+  if (per_cu <= 0 || cus <= 0) return 0;
+  const double resident = (double)per_cu * cus;
+  const double cols = (double)(g.ne / nl) * g.nchunk;
+  int best = 0;
+  double best_cost = 0.0;
+  for (int seg = 1; seg <= nl; ++seg) {
+    if (nl % seg) continue;
+    const double R = cols * (nl / seg) / resident;
+    const double eff = R / std::ceil(R);
+    const double cost = (1.0 + 0.2 / seg) / eff;
+    if (best == 0 || cost < best_cost) {
+      best = seg;
+      best_cost = cost;
+    }
+  }
+  return best >= 2 ? best : 0;
 }
 
 bool hex_one_lane(int order, int precision) {

@@ -18,6 +18,9 @@ int velocities_per_block(int dim, int order, int precision);
 // stage kernels (else the plane-split ones).
 bool hex_one_lane(int order, int precision);
 
+// Elements per work item of the column-sweep stage kernels for this mesh,
+// velocity grid and storage precision on the current device (0: no sweep).
+int sweep_segment(const DevGeom& g, int precision, bool collide);
 // mode 0: fused RK stage (a variant that does not read f^n when a = 0);
 // 1: residual L(f) in FP64; 2: moment partials only.
 hipError_t launch_stage(int precision, int mode, const StageArgs& A, hipStream_t s);

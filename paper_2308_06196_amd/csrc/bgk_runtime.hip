@@ -308,6 +308,7 @@ struct bgk_solver {
   size_t used = 0;
   std::vector<int> kinds;
   int cur = 0;  // state buffer (BF16 storage alternates between f(0) and f(1))
+  int sweep_seg = 0;  // column sweeps of the RK stages: elements per work item (0: none)
   void* f(int b) const { return ws + L.f[b]; }
   void* state() const { return f(cur); }
   double* partials() const { return (double*)(ws + L.partials); }
@@ -392,6 +393,7 @@ StageArgs stage_args(const bgk_solver* s) {
     for (int pos = 0; pos < 2; ++pos) {
       const double* lown = pos ? o.lamL : o.lamR;
       const double* gin = pos ? o.GL : o.GR;
+      for (int i = 0; i < n1; ++i) lo.G[pos][i] = (float)gin[i];
       for (int i = 0; i < n1; ++i)
         for (int k = 0; k < n1; ++k) {
           lo.Dp[pos][i][k] = (float)(o.D[i][k] - gin[i] * lown[k]);
@@ -412,6 +414,7 @@ StageArgs stage_args(const bgk_solver* s) {
   A.out_e0 = 0;
   A.limiter = s->pb.limiter;
   A.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
+  A.sweep_seg = s->sweep_seg;
   for (int k = 0; k < 2; ++k)
     for (int sd = 0; sd < 2; ++sd) A.wall_off[k][sd] = -1;
   if (s->wall.nside) {
@@ -700,6 +703,7 @@ void init_solver(bgk_solver* s, const bgk_problem* pb, char* ws, hipStream_t str
       s->rcols_host[c] = row_cols(g, c * vb, (int)std::min<int64_t>((int64_t)(c + 1) * vb, g.nv));
   }
   setup_walls(s);
+  if (brick) s->sweep_seg = sweep_segment(g, pb->precision, pb->mu_ref > 0.0);
 }
 
 }  // namespace
