@@ -719,10 +719,11 @@ __device__ __forceinline__ bool quads_agree(bool pos) {
 // with FP32 storage (6-7 % faster than 4 on the 32^2 p = 3 box), 4 with BF16
 // increments (whose second value per neighbour node spills at 5, which
 // doubled the time), 3 in FP64; hexahedra (one lane per velocity with all
-// (p+1)^3 nodes) 3 at p = 2 in FP32 arithmetic and 2 in FP64 (three spill
-// and took 2.5x as long), 2 at p = 3 (measured: a few spilled registers at
-// p = 3 cost less than halving the waves; at p = 2 four waves' spills cost a
-// third of the time).
+// (p+1)^3 nodes) 4 at p = 2 in FP32 arithmetic (128 registers without
+// spills since the relaxation is formed before f^n is loaded; Mach-2 box
+// 19.8 against 21.2 ms at three) and 2 in FP64 (three spill and took 2.5x as
+// long), 2 at p = 3 (measured: a few spilled registers at p = 3 cost less
+// than halving the waves).
 template <int DIM, int P, typename CT, bool INC>
 constexpr int stage_waves() {
   return DIM == 3 && P == 3 ? 2
