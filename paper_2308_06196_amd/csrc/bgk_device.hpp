@@ -1051,6 +1051,15 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int chunk, 
 #pragma unroll
             for (int ia = 0; ia < N1; ++ia) acc[base + ia * S1] = fmaf(as, c[ia], acc[base + ia * S1]);
           }
+          // sweep: the last axis loads nothing; keeping its products apart
+          // from the previous axis' (whose loads may still be issued during
+          // the axis before it) leaves the element without spills (80-116
+          // bytes per lane otherwise). A barrier after every axis also
+          // removed them, but then no neighbour load was issued early and
+          // the launch took 40 % longer.
+          if constexpr (SW) {
+            if (k == KS - 1) __builtin_amdgcn_sched_barrier(0);
+          }
         }
         if constexpr (SW) {
           if (k == KS) sweep_store<N1, NT, kTrLds>(fr.r[up ? 0 : 1], f, trl, tr, tid);

@@ -232,13 +232,13 @@ __device__ __forceinline__ void stage3_item(const StageArgs& A, const int chunk,
   CT f[P2];
 #pragma unroll
   for (int q = 0; q < P2; ++q) f[q] = (CT)fe[q * kVB];
-  // sweep: the z-neighbour's planes are not held (see the z part). FP64
-  // arithmetic loads the neighbours' planes one axis at a time (the next
-  // axis' after this axis' transport), so that no more than one neighbour's
-  // planes are held at once; FP32 arithmetic loads them all in the first
-  // batch.
+  // sweep: the z-neighbour's planes are not held (see the z part). The
+  // neighbours' planes are loaded one axis at a time (the next axis' after
+  // this axis' transport), so that no more than one neighbour's planes are
+  // held at once: FP64 fits three waves per SIMD (167 registers against 234
+  // with all loaded up front), BF16 increments four (128 against 157).
   constexpr int NB = SW ? 2 : 3;
-  constexpr bool kStaged = sizeof(CT) == 8;
+  constexpr bool kStaged = true;
   CT nb[NB][P2];
   if constexpr (kStaged) {
     load_planes<P2, kDin>(nb[0], src[0], fin, din);
@@ -530,10 +530,17 @@ __device__ __forceinline__ void stage3_item(const StageArgs& A, const int chunk,
   }
 }
 
-// Three waves per SIMD (FP64: the neighbours' planes loaded one axis at a
-// time fit 168 registers).
+// Waves per SIMD of the plane-split kernels: three in FP64, four in FP32
+// arithmetic (the neighbours' planes loaded one axis at a time); the FP64
+// sweep keeps two (its loop spills at three).
+template <typename CT, bool SW>
+constexpr int plane_waves() {
+  return sizeof(CT) == 8 ? (SW ? 2 : 3) : 4;
+}
+
 template <int P, typename ST, int MODE, bool INC = false>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(plane_waves<typename Compute<ST>::T, false>())))
     k_stage3(const StageArgs A) {
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   stage3_item<P, ST, MODE, INC>(A, (int)(w / A.ecount), work_element(A.order, A.e0, w, A.ecount),
@@ -543,7 +550,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 // Plane-split stage as column sweeps along z (see k_stage_sweep).
 template <int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(typename Compute<ST>::T) == 8 ? 2 : 3)))
+    __attribute__((amdgpu_waves_per_eu(plane_waves<typename Compute<ST>::T, true>())))
     k_stage3_sweep(const StageArgs A) {
   const DevGeom& g = A.g;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);

@@ -727,16 +727,17 @@ static int sweep_groups(int dim, int order, bool inc, size_t tab) {
 // a length that does not divide the column length means no sweep).
 // Sweeps are used where they measured faster than the per-element kernels
 // (ms per stage launch, sweep / per element): quadrilaterals in FP64 (32^2
-// box, p = 3: 1.021 / 1.039), p = 3 hexahedra in FP32 (Taylor-Green box,
-// one lane per velocity: 3.46 / 3.50) and with BF16 increments (plane-split:
-// 6.34 / 6.46). Not for FP32 and BF16 quadrilaterals (0.626 / 0.588, the
-// loop costs registers at five waves per SIMD), p = 2 hexahedra (Mach-2 box
-// at four waves per SIMD: spills) or FP64 p = 3 hexahedra (the plane-split
-// sweep needs two waves per SIMD where the per-element kernel runs three:
-// 10.2 / 9.88).
+// box, p = 3: 1.021 / 1.039) and p = 3 hexahedra in FP32 (Taylor-Green box,
+// one lane per velocity: 3.26 / 3.50; the sweep's last axis loads nothing,
+// and without its loads the element fits the registers). Not for FP32 and
+// BF16 quadrilaterals (0.626 / 0.588, the loop costs registers at five waves
+// per SIMD), p = 2 hexahedra (Mach-2 box at four waves per SIMD: spills),
+// FP64 p = 3 hexahedra (the plane-split sweep needs two waves per SIMD where
+// the per-element kernel runs three: 10.2 / 9.88) or BF16 increments at
+// p = 3 (plane-split at four waves per SIMD: 7.36 / 5.84).
 static bool sweep_pays(const DevGeom& g, int precision) {
   if (g.dim == 2) return precision == 0;
-  return g.dim == 3 && g.n1 == 4 && precision != 0;
+  return g.dim == 3 && g.n1 == 4 && precision == 1;
 }
 
 int sweep_segment(const DevGeom& g, int precision, bool collide) {
