@@ -11,10 +11,11 @@ path, "mixed_bf16" the path with an FP32 state and BF16 stage increments;
 "roofline" the dominant kernel (fused stage) against HBM peak;
 "collision_conservation" the largest relative discrete moment of the collision
 term of each path's final state; "workloads" the 3-D Taylor-Green box (FP32,
-BF16 increments, FP64) and the Mach-2 box (FP32), each with its roofline entry;
-"serving" the request mix (batched server against the plain FP64 path);
-"cpu_baseline" the FP64 oracle timed on a bounded sample on the host's cores
-(all of them and one).
+BF16 increments, FP64), the Mach-2 box (FP32) and the shock tube (FP64, its
+100 steps), each with its roofline entry; "serving" the request mix (batched
+server against the plain FP64 path); "cpu_baseline" the FP64 oracle timed on
+a bounded sample on the host's cores (all of them and one), and on the whole
+shock tube (100 steps, all cores).
 """
 from __future__ import annotations
 
@@ -192,6 +193,26 @@ def cpu_baseline(pb_full, prim_fn, budget_s=12.0):
                       f"direct velocity sums"}
 
 
+def cpu_full_run(pb, prim_fn, steps):
+    """FP64 oracle (plain, untuned) on the whole workload for `steps` SSP-RK3
+    steps (the shock tube: small enough to run in full within the bounded CPU
+    budget); DOF-updates/s."""
+    from oracle import oracle as orc
+    keys = ["dim", "order", "nelem", "xlo", "xhi", "nvel", "vlo", "vhi", "bc", "mu_ref",
+            "theta_ref", "omega", "gamma", "limiter", "newton_maxit", "newton_tol"]
+    pr = orc.Problem(**{k: pb[k] for k in keys})
+    f = orc.maxwellian(pr, prim_fn(orc.node_coords(pr)))
+    dt = orc.stable_dt(pr, f, 0.1)
+    t0 = time.perf_counter()
+    f, _ = orc.rk3_step(pr, f, dt, steps)
+    el = time.perf_counter() - t0
+    dof = pr.nx * pr.nv
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": dof * steps / el, "unit": "DOF-updates/s", "cores": threads,
+            "kind": "oracle", "sample": f"the whole workload ({dof} DOF), {steps} SSP-RK3 "
+                                        f"steps, {el:.2f} s, FP64, direct velocity sums"}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -202,14 +223,17 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline_in_process(workload_name, threads, budget_s):
-    """cpu_baseline in a child process with OMP_NUM_THREADS = threads (the
-    oracle's OpenMP team size is fixed when its library loads)."""
+def cpu_baseline_in_process(workload_name, threads, budget_s, full_steps=0):
+    """cpu_baseline (or, with full_steps, cpu_full_run) in a child process with
+    OMP_NUM_THREADS = threads (the oracle's OpenMP team size is fixed when its
+    library loads)."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS=str(threads))
-    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
-                          "--workload", workload_name, "--cpu-budget", str(budget_s)],
-                         env=env, capture_output=True, text=True, check=True)
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+           "--workload", workload_name, "--cpu-budget", str(budget_s)]
+    if full_steps:
+        cmd += ["--cpu-full-steps", str(full_steps)]
+    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True)
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
@@ -282,6 +306,8 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="only time the CPU oracle on the workload's sample and print it")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-full-steps", type=int, default=0, metavar="N",
+                    help="with --cpu-baseline-only: run the whole workload for N steps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times); "
                          "calibrates the HBM byte counters against a known traffic")
@@ -297,7 +323,10 @@ def main():
         return
     if a.cpu_baseline_only:
         pb, prim_fn, _ = workload(a.workload)
-        print(json.dumps(cpu_baseline(pb, prim_fn, a.cpu_budget)), flush=True)
+        if a.cpu_full_steps:
+            print(json.dumps(cpu_full_run(pb, prim_fn, a.cpu_full_steps)), flush=True)
+        else:
+            print(json.dumps(cpu_baseline(pb, prim_fn, a.cpu_budget)), flush=True)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -336,7 +365,7 @@ def main():
         # (FP32), each with the roofline entry of its stage kernel
         line["workloads"] = {}
         for name, prec, steps in (("tgv3d", 1, 5), ("tgv3d", 2, 5), ("tgv3d", 0, 3),
-                                  ("mach2", 1, 3)):
+                                  ("mach2", 1, 3), ("sod1d", 0, 100)):
             wpb, wprim, wdesc = workload(name)
             r = run_gpu(wpb, wprim, prec, steps, 1)
             key = f"{name}_{['fp64', 'fp32', 'bf16'][prec]}"
@@ -363,6 +392,10 @@ def main():
         one = cpu_baseline_in_process(a.workload, 1, a.cpu_budget)
         cb["cpu_model"] = cpu_model()
         cb["single_core"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
+        if a.workload == "box2d":
+            # the shock tube (32 elements, p = 2, 16^3 velocities) in full, 100 steps
+            c1 = cpu_baseline_in_process("sod1d", threads, a.cpu_budget, full_steps=100)
+            cb["sod1d_full"] = {"value": c1["value"], "cores": c1["cores"], "sample": c1["sample"]}
         line["cpu_baseline"] = cb
         print(f"[bench] cpu baseline {line['cpu_baseline']}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
