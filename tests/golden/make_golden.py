@@ -1,6 +1,6 @@
 """Write the oracle's long-run moment fixtures (FP64 CPU oracle only).
 
-    python tests/golden/make_golden.py [box2d] [tgv3d_n8]
+    python tests/golden/make_golden.py [box2d] [tgv3d_n8] [mach2_n8]
 
 Each fixture is the oracle's per-node moments Q [nx][5] = (rho, rho U, E)
 after a full run, stored as ``<name>_q.npy`` with ``<name>.json`` beside it
@@ -14,6 +14,11 @@ seeded workload generators; every number written is the oracle's.
             grid (16^3 on [-5,5]^3), Knudsen number and initial state on a
             reduced mesh of 8^3 elements, 100 SSP-RK3 steps (the time step is
             bounded by the relaxation time, as on the full mesh).
+  mach2_n8  3-D Mach-2 box with the full case's order (p = 2), velocity grid
+            (20^3 on [-8,8]^3), Knudsen number and seeded initial state (Mach-2
+            stream plus 5 % density and temperature modes) on a reduced mesh of
+            8^3 elements, its 50 SSP-RK3 steps (the full case in FP64 needs
+            about 170 GB).
 """
 import json
 import os
@@ -58,7 +63,11 @@ def tgv3d_n8():
     _run("tgv3d_n8", wl.tgv3d(n=8), "tgv3d", 100)
 
 
+def mach2_n8():
+    _run("mach2_n8", wl.mach2(n=8), "mach2", 50)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["box2d", "tgv3d_n8"]
+    which = sys.argv[1:] or ["box2d", "tgv3d_n8", "mach2_n8"]
     for w in which:
-        {"box2d": box2d, "tgv3d_n8": tgv3d_n8}[w]()
+        {"box2d": box2d, "tgv3d_n8": tgv3d_n8, "mach2_n8": mach2_n8}[w]()

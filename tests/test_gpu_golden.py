@@ -4,13 +4,17 @@ Fixtures (tests/golden/make_golden.py, written by the FP64 oracle alone):
   box2d     the 2-D periodic box at full size (32x32 elements, p = 3, 24^3
             velocities), 200 SSP-RK3 steps;
   tgv3d_n8  the 3-D Taylor-Green box's order, velocity grid, Knudsen number
-            and initial state on 8^3 elements, 100 steps.
+            and initial state on 8^3 elements, 100 steps;
+  mach2_n8  the 3-D Mach-2 box's order (p = 2), velocity grid (20^3 on
+            [-8,8]^3), Knudsen number and seeded initial state on 8^3
+            elements, its 50 steps (the full box in FP64 does not fit the
+            oracle's host memory).
 The GPU runs each in FP64 storage, FP32 storage and BF16 increments with the
 fixture's time step and reports the Gauss-weighted L2 relative error of rho,
 rho U (normalised by ||rho||) and E against the oracle.
 
 Gates: FP64 1e-12 on every field (measured 2.9e-15 on box2d, 1.3e-14 on
-tgv3d_n8). FP32 and BF16: ten times the largest field error measured on the
+tgv3d_n8, 3.4e-15 on mach2_n8). FP32 and BF16: ten times the largest field error measured on the
 MI355X when the gates were set (stated beside each gate).
 
 The L2 error of f itself (weights: element Jacobian x Gauss x trapezoid) is
@@ -34,10 +38,12 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 # field-error gates (FP32 storage, BF16 increments): 10x the largest measured
 # field error. Measured (rho, rho U, E): box2d FP32 4.03e-6, 4.05e-7, 4.02e-6;
 # BF16 1.41e-5, 1.02e-5, 1.99e-5; tgv3d_n8 FP32 2.17e-6, 1.79e-7, 2.17e-6;
-# BF16 2.18e-6, 1.80e-7, 2.20e-6.
+# BF16 2.18e-6, 1.80e-7, 2.20e-6; mach2_n8 FP32 1.18e-6, 3.09e-6, 1.20e-6;
+# BF16 2.05e-5, 6.05e-5, 2.64e-5 (FP64 3.4e-15).
 GATES = {
     "box2d": {1: 4.1e-5, 2: 2.0e-4},
     "tgv3d_n8": {1: 2.2e-5, 2: 2.2e-5},
+    "mach2_n8": {1: 3.1e-5, 2: 6.1e-4},
 }
 
 
@@ -53,7 +59,7 @@ def _fixture(name):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("name", ["box2d", "tgv3d_n8"])
+@pytest.mark.parametrize("name", ["box2d", "tgv3d_n8", "mach2_n8"])
 def test_long_run_fields_against_oracle(name):
     import torch
     from paper_2308_06196_amd import bgk
