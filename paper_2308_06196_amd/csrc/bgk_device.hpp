@@ -143,6 +143,7 @@ struct StageArgs {
   const RowCols* rcols;
   int32_t rc_mask;
   int32_t sweep_seg;  // column sweeps: elements per work item along the last axis
+  int32_t xcd_part;   // XCDs per chunk group of xcd_chunk_remap (else xcd_remap)
 };
 
 // BF16 <-> FP32: the upper half of the FP32 bit pattern; rounding to nearest,
@@ -193,6 +194,24 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   const int64_t x = bid % kNumXCD, k = bid / kNumXCD;
   const int64_t per = nb / kNumXCD, rem = nb % kNumXCD;
   return x * per + (x < rem ? x : rem) + k;
+}
+
+// Linear block id -> work id with groups of `part` XCDs (8, 4 or 2) sharing
+// one velocity chunk at a time: XCD x of group x / part takes the
+// (x % part)-th share of every chunk the group walks, so that the XCDs of a
+// group hold neighbouring work items of one chunk together and a neighbour
+// read that misses one XCD's L2 finds nodes that another XCD has just
+// fetched into the memory-side cache. per_chunk work items per chunk,
+// nb = chunks x per_chunk; other part values or sizes: contiguous ranges.
+__device__ __forceinline__ int64_t xcd_chunk_remap(int64_t bid, int64_t nb, int64_t per_chunk,
+                                                   int32_t part) {
+  if (part != 2 && part != 4 && part != 8) return xcd_remap(bid, nb);
+  const int ng = kNumXCD / part;
+  if (per_chunk % part != 0 || (nb / per_chunk) % ng != 0) return xcd_remap(bid, nb);
+  const int64_t x = bid % kNumXCD, k = bid / kNumXCD;
+  const int64_t s = per_chunk / part, r = k / s;
+  const int64_t c = r * ng + x / part;
+  return c * per_chunk + (x % part) * s + (k - r * s);
 }
 
 // Element of work item w (velocity-chunk major): the k-th element of the
@@ -1270,7 +1289,7 @@ template <int DIM, int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
     k_stage(const StageArgs A) {
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t w = xcd_chunk_remap(blockIdx.x, gridDim.x, A.ecount, A.xcd_part);
   typename Compute<ST>::T tr[sweep_tr_regs<DIM, P>()];
   stage_item<DIM, P, ST, MODE, INC>(A, (int)(w / A.ecount), work_element(A.order, A.e0, w, A.ecount),
                                     w == 0, false, false, tr);
@@ -1311,9 +1330,9 @@ __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, P, typename Compute<ST>::T, INC>())))
     k_stage_sweep(const StageArgs A) {
   const DevGeom& g = A.g;
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int nl = sreg(g.nelem[DIM - 1]), seg = sreg(A.sweep_seg);
   const int64_t ncol = g.ne / nl, nseg = nl / seg, per_chunk = ncol * nseg;
+  const int64_t w = xcd_chunk_remap(blockIdx.x, gridDim.x, per_chunk, A.xcd_part);
   const int chunk = (int)(w / per_chunk);
   const int64_t r = w - (int64_t)chunk * per_chunk;
   const int64_t sg = r / ncol, col = r - sg * ncol;

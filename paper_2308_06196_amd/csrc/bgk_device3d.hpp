@@ -542,7 +542,7 @@ template <int P, typename ST, int MODE, bool INC = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(plane_waves<typename Compute<ST>::T, false>())))
     k_stage3(const StageArgs A) {
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t w = xcd_chunk_remap(blockIdx.x, gridDim.x, A.ecount, A.xcd_part);
   stage3_item<P, ST, MODE, INC>(A, (int)(w / A.ecount), work_element(A.order, A.e0, w, A.ecount),
                                 w == 0, false, false);
 }
@@ -553,9 +553,9 @@ __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(plane_waves<typename Compute<ST>::T, true>())))
     k_stage3_sweep(const StageArgs A) {
   const DevGeom& g = A.g;
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int nl = sreg(g.nelem[2]), seg = sreg(A.sweep_seg);
   const int64_t ncol = g.ne / nl, nseg = nl / seg, per_chunk = ncol * nseg;
+  const int64_t w = xcd_chunk_remap(blockIdx.x, gridDim.x, per_chunk, A.xcd_part);
   const int chunk = (int)(w / per_chunk);
   const int64_t r = w - (int64_t)chunk * per_chunk;
   const int64_t sg = r / ncol, col = r - sg * ncol;

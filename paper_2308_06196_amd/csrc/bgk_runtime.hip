@@ -8,6 +8,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -309,6 +310,7 @@ struct bgk_solver {
   std::vector<int> kinds;
   int cur = 0;  // state buffer (BF16 storage alternates between f(0) and f(1))
   int sweep_seg = 0;  // column sweeps of the RK stages: elements per work item (0: none)
+  int xcd_part = 0;   // stage work items dealt to the XCDs chunk by chunk (xcd_chunk_remap)
   void* f(int b) const { return ws + L.f[b]; }
   void* state() const { return f(cur); }
   double* partials() const { return (double*)(ws + L.partials); }
@@ -415,6 +417,7 @@ StageArgs stage_args(const bgk_solver* s) {
   A.limiter = s->pb.limiter;
   A.collide = s->pb.mu_ref > 0.0 ? 1 : 0;
   A.sweep_seg = s->sweep_seg;
+  A.xcd_part = s->xcd_part;
   for (int k = 0; k < 2; ++k)
     for (int sd = 0; sd < 2; ++sd) A.wall_off[k][sd] = -1;
   if (s->wall.nside) {
@@ -704,6 +707,19 @@ void init_solver(bgk_solver* s, const bgk_problem* pb, char* ws, hipStream_t str
   }
   setup_walls(s);
   if (brick) s->sweep_seg = sweep_segment(g, pb->precision, pb->mu_ref > 0.0);
+  if (brick) {
+    // XCDs sharing a velocity chunk in the stage launches (xcd_chunk_remap):
+    // all eight for column sweeps (tgv3d FP32 3.15 against 3.25 ms per
+    // launch, box2d FP64 1 % faster), four for the plane-split hexahedra
+    // (tgv3d FP64 1.5 %, BF16 increments 1 % faster); contiguous ranges for
+    // the per-element one-lane kernels (the Mach-2 box 2 % slower with eight).
+    // BGK_XCD_PART overrides the choice (0: contiguous ranges).
+    const char* env = getenv("BGK_XCD_PART");
+    s->xcd_part = env                                            ? atoi(env)
+                  : s->sweep_seg > 0                             ? 8
+                  : pb->dim == 3 && !hex_one_lane(pb->order, pb->precision) ? 4
+                                                                 : 0;
+  }
 }
 
 }  // namespace
