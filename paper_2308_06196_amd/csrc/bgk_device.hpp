@@ -149,6 +149,41 @@ struct StageArgs {
 // BF16 <-> FP32: the upper half of the FP32 bit pattern; rounding to nearest,
 // ties to even (finite inputs).
 __device__ __forceinline__ float bf16_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// BF16 increment buffers pair the nodes of a velocity block: the increments
+// of nodes 2m and 2m + 1 of a velocity share one 32-bit word (node 2m in the
+// low half), word m * 64 + lane of the pair's 128 halves, so that a lane
+// reads or writes two node values with one access; an odd last node of the
+// block keeps its 64 halves (one per lane). The buffers have the state's
+// size and block offsets. off = f_offset of an even node a of a block at the
+// lane; the words of nodes a + 2m, a + 2m + 1 follow at m * 64.
+__device__ __forceinline__ const uint32_t* inc_pairs(const uint16_t* d, int64_t off) {
+  return (const uint32_t*)(d + (off & ~(int64_t)(kVB - 1))) + (off & (kVB - 1));
+}
+__device__ __forceinline__ uint32_t* inc_pairs(uint16_t* d, int64_t off) {
+  return (uint32_t*)(d + (off & ~(int64_t)(kVB - 1))) + (off & (kVB - 1));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+// v[i] += increment of node a + i, i < N (N odd: the block's last nodes)
+template <int N, typename CT>
+__device__ __forceinline__ void add_increments(CT (&v)[N], const uint16_t* d, int64_t off) {
+  const uint32_t* w = inc_pairs(d, off);
+#pragma unroll
+  for (int m = 0; m < N / 2; ++m) {
+    const uint32_t x = w[m * kVB];
+    v[2 * m] += bf16_lo(x);
+    v[2 * m + 1] += bf16_hi(x);
+  }
+  if constexpr (N % 2 != 0) v[N - 1] += bf16_f32(d[off + (N - 1) * kVB]);
+}
+// increment of node a + i alone (i < N, as above)
+template <int N>
+__device__ __forceinline__ float increment_of(const uint16_t* d, int64_t off, int i) {
+  if (N % 2 != 0 && i == N - 1) return bf16_f32(d[off + i * kVB]);
+  const uint32_t x = inc_pairs(d, off)[(i >> 1) * kVB];
+  return (i & 1) ? bf16_hi(x) : bf16_lo(x);
+}
 __device__ __forceinline__ uint16_t f32_bf16(float x) {
   uint32_t u = __float_as_uint(x);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -927,20 +962,12 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int chunk, 
 #pragma unroll
     for (int i = 0; i < NS; ++i) fb[i] = f[i];
   }
-  if constexpr (kDin) {
-    const uint16_t* de = din + (fe - fin);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) f[i] += bf16_f32(de[i * kVB]);
-  }
+  if constexpr (kDin) add_increments(f, din, fe - fin);
   CT nbv[kPreload ? DIM : 1][kPreload ? NS : 1];
   if constexpr (kPreload) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) nbv[0][i] = (CT)src[0][i * kVB];
-    if constexpr (kDin) {
-      const uint16_t* ds = din + (src[0] - fin);
-#pragma unroll
-      for (int i = 0; i < NS; ++i) nbv[0][i] += bf16_f32(ds[i * kVB]);
-    }
+    if constexpr (kDin) add_increments(nbv[0], din, src[0] - fin);
   }
   // the needed entries of this element's equilibrium rows -> LDS
   if (A.collide) {
@@ -968,11 +995,7 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int chunk, 
         if (ld) {
 #pragma unroll
           for (int i = 0; i < NS; ++i) nbv[k][i] = (CT)src[k][i * kVB];
-          if constexpr (kDin) {
-            const uint16_t* ds = din + (src[k] - fin);
-#pragma unroll
-            for (int i = 0; i < NS; ++i) nbv[k][i] += bf16_f32(ds[i * kVB]);
-          }
+          if constexpr (kDin) add_increments(nbv[k], din, src[k] - fin);
         }
       }
     }
@@ -982,7 +1005,7 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int chunk, 
         return nbv[k][i];
       } else {
         CT xv = (CT)src[k][i * kVB];
-        if constexpr (kDin) xv += bf16_f32(din[(src[k] - fin) + i * kVB]);
+        if constexpr (kDin) xv += increment_of<NS>(din, src[k] - fin, i);
         return xv;
       }
     };
@@ -1253,13 +1276,21 @@ __device__ __forceinline__ void stage_item(const StageArgs& A, const int chunk, 
           for (int i = 0; i < NS; ++i) __builtin_nontemporal_store((ST)o[i], &oe[i * kVB]);
         }
       } else {
-        uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, 0, jj);
+        const int64_t ooff = f_offset(g, e, 0, jj);
+        uint32_t* ow = inc_pairs((uint16_t*)A.out, ooff);
         float omin = INFINITY, smin = INFINITY;  // stage values / stored values
+        uint32_t hp = 0;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           float stored;
           const uint16_t h = bf16_increment(o[i], fnv[i], stored);
-          if (valid) __builtin_nontemporal_store(h, &oe[i * kVB]);
+          if (i % 2 == 0 && i == NS - 1) {
+            if (valid) __builtin_nontemporal_store(h, (uint16_t*)A.out + ooff + i * kVB);
+          } else if (i % 2 == 0) {
+            hp = h;
+          } else if (valid) {
+            __builtin_nontemporal_store(hp | ((uint32_t)h << 16), &ow[(i >> 1) * kVB]);
+          }
           omin = fminf(omin, o[i]);
           smin = fminf(smin, stored);
           o[i] = stored;

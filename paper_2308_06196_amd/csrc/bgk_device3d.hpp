@@ -112,11 +112,7 @@ __device__ __forceinline__ void load_planes(CT (&v)[P2], const ST* src, const ST
                                             const uint16_t* din) {
 #pragma unroll
   for (int q = 0; q < P2; ++q) v[q] = (CT)src[q * kVB];
-  if constexpr (DIN) {
-    const uint16_t* ds = din + (src - fin);
-#pragma unroll
-    for (int q = 0; q < P2; ++q) v[q] += bf16_f32(ds[q * kVB]);
-  }
+  if constexpr (DIN) add_increments(v, din, src - fin);
 }
 
 template <int P, typename ST, int MODE, bool INC = false, bool SW = false>
@@ -249,16 +245,10 @@ __device__ __forceinline__ void stage3_item(const StageArgs& A, const int chunk,
       for (int q = 0; q < P2; ++q) nb[k][q] = (CT)src[k][q * kVB];
   }
   if constexpr (kDin) {
-    const uint16_t* de = din + (fe - fin);
-#pragma unroll
-    for (int q = 0; q < P2; ++q) f[q] += bf16_f32(de[q * kVB]);
+    add_increments(f, din, fe - fin);
     if constexpr (!kStaged) {
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const uint16_t* ds = din + (src[k] - fin);
-#pragma unroll
-        for (int q = 0; q < P2; ++q) nb[k][q] += bf16_f32(ds[q * kVB]);
-      }
+      for (int k = 0; k < NB; ++k) add_increments(nb[k], din, src[k] - fin);
     }
   }
 
@@ -368,7 +358,7 @@ __device__ __forceinline__ void stage3_item(const StageArgs& A, const int chunk,
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
           CT v = (CT)src[2][q * kVB];
-          if constexpr (kDin) v += bf16_f32(din[(src[2] - fin) + q * kVB]);
+          if constexpr (kDin) v += increment_of<P2>(din, src[2] - fin, q);
           const CT t = group_allsum<G>(lext_mine * v);
           if (!lane_carry) trl[q * VB + vg] = t;
         }
@@ -501,13 +491,19 @@ __device__ __forceinline__ void stage3_item(const StageArgs& A, const int chunk,
           for (int q = 0; q < P2; ++q) __builtin_nontemporal_store((ST)o[q], &oe[q * kVB]);
         }
       } else {
-        uint16_t* oe = (uint16_t*)A.out + f_offset(g, e, pl * P2, jj);
+        static_assert(P2 % 2 == 0, "BF16 planes hold whole node pairs");
+        uint32_t* ow = inc_pairs((uint16_t*)A.out, f_offset(g, e, pl * P2, jj));
         float omin = INFINITY, smin = INFINITY;  // stage values / stored values
+        uint32_t hp = 0;
 #pragma unroll
         for (int q = 0; q < P2; ++q) {
           float stored;
           const uint16_t h = bf16_increment(o[q], fnv[q], stored);
-          if (act) __builtin_nontemporal_store(h, &oe[q * kVB]);
+          if (q % 2 == 0) {
+            hp = h;
+          } else if (act) {
+            __builtin_nontemporal_store(hp | ((uint32_t)h << 16), &ow[(q >> 1) * kVB]);
+          }
           omin = fminf(omin, o[q]);
           smin = fminf(smin, stored);
           o[q] = stored;

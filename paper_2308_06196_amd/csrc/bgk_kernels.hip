@@ -560,7 +560,9 @@ static void launch_sweep(bool inc, const StageArgs& A, size_t lds, hipStream_t s
 template <int P, typename ST>
 static void launch_sweep3(bool inc, const StageArgs& A, size_t lds, hipStream_t s) {
   const dim3 grid = sweep_grid(A), block(kBlock);
-  if constexpr (sizeof(ST) == 4) {
+  // BF16 increments on planes of whole node pairs (odd p; p = 3 is the one
+  // that runs plane-split, kHexOneLane)
+  if constexpr (sizeof(ST) == 4 && Plane3<P>::P2 % 2 == 0) {
     if (inc) {
       if (A.din)
         hipLaunchKernelGGL((k_stage3_sweep<P, ST, 0, true>), grid, block, lds, s, A);
@@ -609,7 +611,7 @@ static hipError_t hex_dispatch(int mode, bool inc, const StageArgs& A, size_t ta
   if (sweep) {
     launch_sweep3<P, ST>(inc, A, lds3, s);
   } else if (mode == 0 && inc) {
-    if constexpr (sizeof(ST) == 4) {
+    if constexpr (sizeof(ST) == 4 && Plane3<P>::P2 % 2 == 0) {
       if (A.din)
         hipLaunchKernelGGL((k_stage3<P, ST, 0, true>), grid, block, lds3, s, A);
       else
@@ -688,7 +690,7 @@ static int sweep_groups_per_cu(bool inc, size_t tab) {
   if constexpr (D == 3) {
     if (!kHexOneLane<P, ST>(inc)) {
       const size_t lds = std::max(tab, (size_t)mfma3_lds_bytes<P, ST>());
-      if constexpr (sizeof(ST) == 4) {
+      if constexpr (sizeof(ST) == 4 && Plane3<P>::P2 % 2 == 0) {
         if (inc) return groups_per_cu(k_stage3_sweep<P, ST, 0, true>, lds);
       }
       return groups_per_cu(k_stage3_sweep<P, ST, 0>, lds);
