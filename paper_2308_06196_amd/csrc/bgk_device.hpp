@@ -770,9 +770,10 @@ __device__ __forceinline__ bool quads_agree(bool pos) {
 }
 
 // Waves per SIMD the stage kernel is built for: segments and quadrilaterals 5
-// with FP32 storage (6-7 % faster than 4 on the 32^2 p = 3 box), 4 with BF16
-// increments (whose second value per neighbour node spills at 5, which
-// doubled the time), 3 in FP64; hexahedra (one lane per velocity with all
+// with FP32 storage (6-7 % faster than 4 on the 32^2 p = 3 box) and with BF16
+// increments (one 32-bit load per two node increments; 3 spilled registers
+// in stages 2-3 at p = 3, 2.5 % faster than 4 on that box, where one 16-bit
+// load per increment spilled enough to double the time), 3 in FP64; hexahedra (one lane per velocity with all
 // (p+1)^3 nodes) 4 at p = 2 in FP32 arithmetic (128 registers without
 // spills since the relaxation is formed before f^n is loaded; Mach-2 box
 // 19.8 against 21.2 ms at three) and 2 in FP64 (three spill and took 2.5x as
@@ -782,7 +783,7 @@ template <int DIM, int P, typename CT, bool INC>
 constexpr int stage_waves() {
   return DIM == 3 && P == 3 ? 2
          : DIM == 3 && P == 2 ? (sizeof(CT) == 8 ? 2 : 4)
-         : sizeof(CT) == 8 ? 3 : INC ? 4 : 5;
+         : sizeof(CT) == 8 ? 3 : 5;
 }
 
 // ---------------------------------------------------------------------------
