@@ -245,7 +245,8 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
     stream at 0.8 x that rate. The comparator is the plain FP64 path: the same
     kernels launched directly, one request at a time in arrival order, no
     overlap, on the same two arrival patterns, timed on the wall clock with the
-    same set-up work per request (solver, initial state, time step)."""
+    same set-up work per request (solver, initial state, time step). Both take
+    the requests' workspaces from one device arena of the pool's size."""
     from paper_2308_06196_amd import serve
     from paper_2308_06196_amd import workloads as wl
     pool = int(pool_gb * (1 << 30))
@@ -255,7 +256,7 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
                                                        steps=steps, kinds=kinds))
 
     def batched(rate):
-        ex = serve.BatchExecutor(max_members=max_members)
+        ex = serve.BatchExecutor(max_members=max_members, arena_bytes=pool)
         m = serve.Server(ex, pool, max_members=max_members, quantum=quantum,
                          policy=policy).run(reqs(rate))
         ex.close()
@@ -270,12 +271,12 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
     cap_rate = sat["completed"] / sat["span_s"]
     pois = batched(0.8 * cap_rate)
     say("batched, Poisson", pois)
-    seq_sat = serve.run_sequential(reqs(None), pool)
+    seq_sat = serve.run_sequential(reqs(None), pool, arena=True)
     say("sequential FP64, all at t = 0", seq_sat)
-    seq_pois = serve.run_sequential(reqs(0.8 * cap_rate), pool)
+    seq_pois = serve.run_sequential(reqs(0.8 * cap_rate), pool, arena=True)
     say("sequential FP64, Poisson", seq_pois)
     return {"requests": n_requests, "steps_each": steps, "kinds": list(kinds),
-            "policy": policy, "max_members": max_members,
+            "policy": policy, "max_members": max_members, "workspaces": "device arena",
             "total_dof": int(sum(r.dof for r in reqs(None))),
             "capacity_requests_per_s": cap_rate, "poisson_rate_per_s": 0.8 * cap_rate,
             "batched_saturating": sat, "batched_poisson": pois,

@@ -57,6 +57,66 @@ class Executor:
     def poll(self) -> list: ...
     def release(self, handle) -> None: ...
 
+    def fits(self, req: Request) -> bool:
+        """Whether `admit` can place the request now (beyond the pool total:
+        an executor with its own arena may be fragmented)."""
+        return True
+
+
+class DeviceArena:
+    """One device allocation that the workspaces of admitted requests are cut
+    from: first fit over the free ranges, a released range merged with its free
+    neighbours, offsets rounded to `align` bytes. Admitting a request then
+    calls no device allocator: a caching allocator that has to return cached
+    blocks to the device to place a large workspace synchronises the device
+    and frees and maps memory while the resident members' queued work runs
+    out. A range is released only once the device has executed every launch
+    that names it (the executors release members after their completion)."""
+
+    def __init__(self, nbytes: int, device="cuda:0", align: int = 1 << 21):
+        import torch
+
+        self.align = int(align)
+        self.nbytes = int(nbytes) // self.align * self.align
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.free = [(0, self.nbytes)]  # (offset, size), sorted by offset, never adjacent
+
+    def _size(self, n: int) -> int:
+        return -(-int(n) // self.align) * self.align
+
+    def fits(self, n: int) -> bool:
+        need = self._size(n)
+        return any(sz >= need for _, sz in self.free)
+
+    def alloc(self, n: int):
+        """(offset, uint8 view of n bytes) of the first free range that holds n."""
+        need = self._size(n)
+        for k, (off, sz) in enumerate(self.free):
+            if sz >= need:
+                if sz == need:
+                    del self.free[k]
+                else:
+                    self.free[k] = (off + need, sz - need)
+                return off, self.buf.narrow(0, off, int(n))
+        raise MemoryError(f"arena: no free range of {need} bytes")
+
+    def release(self, off: int, n: int) -> None:
+        need = self._size(n)
+        k = 0
+        while k < len(self.free) and self.free[k][0] < off:
+            k += 1
+        self.free.insert(k, (off, need))
+        # merge with the following, then with the preceding range
+        if k + 1 < len(self.free) and off + need == self.free[k + 1][0]:
+            self.free[k] = (off, need + self.free[k + 1][1])
+            del self.free[k + 1]
+        if k > 0 and self.free[k - 1][0] + self.free[k - 1][1] == off:
+            self.free[k - 1] = (self.free[k - 1][0], self.free[k - 1][1] + self.free[k][1])
+            del self.free[k]
+
+    def in_use(self) -> int:
+        return self.nbytes - sum(sz for _, sz in self.free)
+
 
 class Server:
     """policy: "fifo" admits arrived requests in arrival order; "sjf" admits the
@@ -107,7 +167,8 @@ class Server:
             # admission by the policy, while memory and slots allow
             while len(self.active) < self.max_members:
                 i = self._next(pending, t)
-                if i is None or self.used + pending[i].footprint > self.capacity:
+                if (i is None or self.used + pending[i].footprint > self.capacity
+                        or not self.ex.fits(pending[i])):
                     break
                 r = pending.pop(i)
                 try:
@@ -170,7 +231,8 @@ class BatchExecutor(Executor):
     workspace; all members run on the batch's stream, each launch covering
     every member of one kernel family."""
 
-    def __init__(self, device="cuda:0", max_members: int = 64, cfl: float = 0.1):
+    def __init__(self, device="cuda:0", max_members: int = 64, cfl: float = 0.1,
+                 arena_bytes: Optional[int] = None):
         import torch
 
         from . import bgk
@@ -182,20 +244,43 @@ class BatchExecutor(Executor):
         self.cfl = cfl
         self.batch = bgk.Batch(self.stream, max_members)
         self.members = {}
+        # workspaces from one arena (arena_bytes) or from torch's allocator
+        self.arena = DeviceArena(arena_bytes, device) if arena_bytes else None
+        self.ranges = {}  # handle -> (arena offset, bytes)
 
     def footprint(self, req: Request) -> int:
         return self.bgk.footprint(req.problem, req.precision)[0]
 
+    def fits(self, req: Request) -> bool:
+        return self.arena is None or self.arena.fits(self.footprint(req))
+
     def admit(self, req: Request):
         # initialise on a side stream (its synchronisation does not wait for
         # the members already running), then move to the batch stream
-        s = self.bgk.Solver(req.problem, precision=req.precision, device=self.device,
-                            stream=self.init_stream)
-        s.set_maxwellian(self.wl.PRIM[req.kind](s.node_coords(), **req.prim_args))
-        dt = s.stable_dt(self.cfl)
-        s.set_stream(self.stream)
-        self.batch.add(s, dt, req.steps)
+        ws, rng = None, None
+        if self.arena is not None:
+            nbytes = self.footprint(req)
+            off, ws = self.arena.alloc(nbytes)
+            rng = (off, nbytes)
+        s = None
+        try:
+            s = self.bgk.Solver(req.problem, precision=req.precision, device=self.device,
+                                stream=self.init_stream, workspace=ws)
+            s.set_maxwellian(self.wl.PRIM[req.kind](s.node_coords(), **req.prim_args))
+            dt = s.stable_dt(self.cfl)
+            s.set_stream(self.stream)
+            self.batch.add(s, dt, req.steps)
+        except Exception:
+            # nothing of this request stays queued once its range is reused
+            if s is not None:
+                s.close()
+            self.init_stream.synchronize()
+            if rng is not None:
+                self.arena.release(*rng)
+            raise
         self.members[id(s)] = s
+        if rng is not None:
+            self.ranges[id(s)] = rng
         return id(s)
 
     def step(self, n: int) -> None:
@@ -216,9 +301,17 @@ class BatchExecutor(Executor):
         # waiting for the batch stream
         s = self.members.pop(handle)
         s.close(sync=False)
+        rng = self.ranges.pop(handle, None)
+        if rng is not None:
+            self.arena.release(*rng)
 
     def close(self):
         self.batch.close()
+        # the arena's memory back to the device for whatever runs next
+        self.arena = None
+        self.ranges.clear()
+        self.torch.cuda.synchronize(self.device)
+        self.torch.cuda.empty_cache()
 
 
 class SequentialExecutor(Executor):
@@ -229,7 +322,7 @@ class SequentialExecutor(Executor):
     and first-come-first-served admission, so its latencies are wall-clock
     times like the batched server's."""
 
-    def __init__(self, device="cuda:0", cfl: float = 0.1):
+    def __init__(self, device="cuda:0", cfl: float = 0.1, arena_bytes: Optional[int] = None):
         import torch
 
         from . import bgk
@@ -239,13 +332,18 @@ class SequentialExecutor(Executor):
         self.cfl = cfl
         self.stream = torch.cuda.Stream(device=device)  # default priority
         self.members = {}  # handle -> [solver, dt, remaining steps]
+        # one request at a time: its workspace is the start of the arena
+        self.arena = DeviceArena(arena_bytes, device) if arena_bytes else None
 
     def footprint(self, req: Request) -> int:
         return self.bgk.footprint(req.problem, req.precision)[0]
 
     def admit(self, req: Request):
+        ws = None
+        if self.arena is not None:
+            ws = self.arena.buf.narrow(0, 0, self.footprint(req))
         s = self.bgk.Solver(req.problem, precision=req.precision, device=self.device,
-                            stream=self.stream)
+                            stream=self.stream, workspace=ws)
         s.set_maxwellian(self.wl.PRIM[req.kind](s.node_coords(), **req.prim_args))
         dt = s.stable_dt(self.cfl)
         self.members[id(s)] = [s, dt, req.steps]
@@ -277,13 +375,18 @@ class SequentialExecutor(Executor):
         for s, _, _ in self.members.values():
             s.close()
         self.members.clear()
+        if self.arena is not None:
+            self.arena = None
+            self.torch.cuda.empty_cache()
 
 
 def run_sequential(requests: List[Request], capacity_bytes: int, device="cuda:0",
-                   cfl: float = 0.1, quantum: int = 10) -> dict:
+                   cfl: float = 0.1, quantum: int = 10, arena: bool = False) -> dict:
     """The plain path for comparison: requests run one at a time in arrival
-    order on the wall clock (set-up included), through the same Server loop."""
-    ex = SequentialExecutor(device=device, cfl=cfl)
+    order on the wall clock (set-up included), through the same Server loop;
+    with arena, their workspaces come from one allocation of capacity_bytes."""
+    ex = SequentialExecutor(device=device, cfl=cfl,
+                            arena_bytes=capacity_bytes if arena else None)
     try:
         return Server(ex, capacity_bytes, max_members=1, quantum=quantum,
                       policy="fifo").run(requests)

@@ -109,6 +109,29 @@ def test_request_loop_completes_mix(torch):
     assert m["p99_s"] >= m["p50_s"] > 0
 
 
+def test_request_loop_with_workspace_arena(torch):
+    """The same kind of mix with every workspace cut from one device arena
+    (the serving benchmark's set-up), in the batched and the plain server:
+    all requests complete and every range is back in the arena at the end."""
+    from paper_2308_06196_amd import serve
+    _say("serve-arena")
+    descs = wl.serving_requests(n=12, seed=3, rate=200.0, nv_choices=(8, 16), steps=10)
+    for d in descs:
+        pb = d["problem"]
+        if pb["dim"] == 2:
+            n = min(pb["nelem"][0], 12)
+            pb["nelem"] = [n, n, 1]
+    cap = 2 << 30
+    ex = serve.BatchExecutor(max_members=8, arena_bytes=cap)
+    m = serve.Server(ex, capacity_bytes=cap, max_members=8, quantum=4).run(
+        serve.make_requests(descs))
+    assert ex.arena.in_use() == 0
+    ex.close()
+    assert m["completed"] == len(descs) and m["failed"] == 0
+    q = serve.run_sequential(serve.make_requests(descs), cap, arena=True)
+    assert q["completed"] == len(descs) and q["failed"] == 0
+
+
 def test_batch_admission_mid_run_matches_solo(torch):
     """Continuous batching: a member admitted after the others have stepped, and a
     member that completes while the others go on, each end bitwise equal to the

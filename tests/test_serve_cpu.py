@@ -148,3 +148,75 @@ def test_sjf_lowers_median_latency_under_saturation():
                                    sleep=clk.sleep, policy=policy).run(reqs)
     assert res["sjf"]["p50_s"] < res["fifo"]["p50_s"]
     assert res["sjf"]["completed"] == res["fifo"]["completed"] == 24
+
+
+def test_arena_first_fit_merge_and_reuse():
+    """The workspace arena (on a host tensor here): first fit, offsets on the
+    alignment, released ranges merged with free neighbours, the whole arena
+    one free range again once everything is released."""
+    a = serve.DeviceArena(64 * 1024, device="cpu", align=1024)
+    assert a.fits(64 * 1024) and not a.fits(64 * 1024 + 1)
+    offs = [a.alloc(n) for n in (1000, 3000, 1024, 5000)]
+    assert [o for o, _ in offs] == [0, 1024, 4096, 5120]
+    assert [v.numel() for _, v in offs] == [1000, 3000, 1024, 5000]
+    assert a.in_use() == 1024 + 3072 + 1024 + 5120
+    # views are disjoint slices of the one buffer
+    for (o, v) in offs:
+        assert v.data_ptr() == a.buf.data_ptr() + o
+    a.release(1024, 3000)          # hole of 3072 between two ranges
+    assert a.free[0] == (1024, 3072)
+    o, _ = a.alloc(2048)           # first fit takes the hole
+    assert o == 1024
+    a.release(0, 1000)
+    a.release(1024, 2048)          # merges with both free neighbours
+    assert a.free[0] == (0, 4096)
+    a.release(4096, 1024)          # merges across: 0 .. 5120 free
+    assert a.free[0] == (0, 5120)
+    a.release(5120, 5000)
+    assert a.free == [(0, 64 * 1024)] and a.in_use() == 0
+    with pytest.raises(MemoryError):
+        a.alloc(64 * 1024 + 1)
+
+
+def test_arena_fragmentation_defers_admission():
+    """A request that fits the pool's total but no free range of the arena
+    waits for a completion instead of failing."""
+    clk = Clock()
+
+    class ArenaFake(FakeExecutor):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.arena = serve.DeviceArena(1 << 16, device="cpu", align=1 << 10)
+            self.rng = {}
+
+        def footprint(self, r):
+            return r.footprint_bytes
+
+        def fits(self, r):
+            return self.arena.fits(r.footprint_bytes)
+
+        def admit(self, r):
+            off, _ = self.arena.alloc(r.footprint_bytes)
+            self.rng[r.id] = (off, r.footprint_bytes)
+            return super().admit(r)
+
+        def release(self, h):
+            self.arena.release(*self.rng.pop(h))
+            super().release(h)
+
+    ex = ArenaFake(clk, rate=1e6)
+    reqs = []
+    # A, B, C fill the arena; A and C finish early, leaving two 16 KiB holes:
+    # D (32 KiB) fits the total but no hole until B is done
+    for i, (kb, steps) in enumerate([(16, 1), (32, 50), (16, 1), (32, 1)]):
+        r = serve.Request(id=i, problem={}, kind="x", prim_args={}, arrival=0.0, steps=steps,
+                          dof=1000)
+        r.footprint_bytes = kb << 10
+        reqs.append(r)
+    m = serve.Server(ex, 1 << 16, max_members=4, quantum=1, clock=clk, sleep=clk.sleep,
+                     policy="fifo").run(reqs)
+    assert m["completed"] == 4 and m["failed"] == 0
+    assert ex.order == [0, 1, 2, 3]
+    d = reqs[3]
+    assert d.admitted >= reqs[1].done  # waited for B's range
+    assert ex.arena.in_use() == 0
