@@ -238,7 +238,7 @@ def cpu_baseline_in_process(workload_name, threads, budget_s, full_steps=0):
 
 
 def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
-            kinds=("sod1d", "box2d"), policy="sjf"):
+            kinds=("sod1d", "box2d"), policy="sjf", large_dof=2.5e8):
     """Serving mix (shock tubes and periodic boxes, p in 1..3, 8^3..32^3 velocities,
     Kn log-uniform [1e-4, 1], 100 steps each). A saturating run (all requests at
     t = 0) measures the capacity; then the same requests arrive as a Poisson
@@ -258,7 +258,7 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
     def batched(rate):
         ex = serve.BatchExecutor(max_members=max_members, arena_bytes=pool)
         m = serve.Server(ex, pool, max_members=max_members, quantum=quantum,
-                         policy=policy).run(reqs(rate))
+                         policy=policy, large_dof=large_dof).run(reqs(rate))
         ex.close()
         return m
 
@@ -277,6 +277,7 @@ def serving(n_requests, steps, seed=0, pool_gb=200.0, max_members=8, quantum=4,
     say("sequential FP64, Poisson", seq_pois)
     return {"requests": n_requests, "steps_each": steps, "kinds": list(kinds),
             "policy": policy, "max_members": max_members, "workspaces": "device arena",
+            "large_dof": large_dof, "max_large": 1,
             "total_dof": int(sum(r.dof for r in reqs(None))),
             "capacity_requests_per_s": cap_rate, "poisson_rate_per_s": 0.8 * cap_rate,
             "batched_saturating": sat, "batched_poisson": pois,
@@ -298,6 +299,9 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=100)
     ap.add_argument("--serving-policy", default="sjf", choices=["fifo", "sjf"],
                     help="admission order of the batched server")
+    ap.add_argument("--serving-large-dof", type=float, default=2.5e8,
+                    help="requests of this many phase-space DOF or more run one at a time "
+                         "beside the small ones (0: no limit)")
     ap.add_argument("--serving-members", type=int, default=8,
                     help="requests resident in the batch at once")
     ap.add_argument("--serving-kinds", default="sod1d,box2d",
@@ -379,7 +383,8 @@ def main():
                   file=sys.stderr, flush=True)
     if a.serving:
         sv = serving(a.serving, a.serving_steps, kinds=tuple(a.serving_kinds.split(",")),
-                     policy=a.serving_policy, max_members=a.serving_members)
+                     policy=a.serving_policy, max_members=a.serving_members,
+                     large_dof=a.serving_large_dof or None)
         line["serving"] = sv
         p, q = sv["batched_poisson"], sv["sequential_fp64_poisson"]
         print(f"[bench] serving {a.serving} requests: batched p50 {p['p50_s']:.3f} s, p99 "

@@ -121,13 +121,29 @@ class DeviceArena:
 class Server:
     """policy: "fifo" admits arrived requests in arrival order; "sjf" admits the
     arrived request with the least work (DOF x steps) first, which lowers the
-    median latency when the pool or the member slots are the bottleneck."""
+    median latency when the pool or the member slots are the bottleneck.
+    large_dof / max_large: requests of large_dof phase-space DOF or more are
+    resident at most max_large at a time (the others wait, small requests go
+    past them); shared by several large solves the device would stretch each
+    one's time to solution by their number."""
 
     def __init__(self, executor: Executor, capacity_bytes: int, max_members: int = 64,
                  quantum: int = 10, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, policy: str = "fifo"):
+                 sleep: Callable[[float], None] = time.sleep, policy: str = "fifo",
+                 max_wait: Optional[float] = None, large_dof: Optional[int] = None,
+                 max_large: int = 1):
         if policy not in ("fifo", "sjf"):
             raise ValueError(policy)
+        # sjf: a request that has waited longer than max_wait seconds goes
+        # first (oldest first), so large requests are not passed over forever
+        self.max_wait = max_wait
+        # at most max_large requests of large_dof phase-space DOF or more are
+        # resident at once: large solves then do not share the device with
+        # each other (each runs at close to its solo speed, which bounds the
+        # tail), while small ones keep joining beside them
+        self.large_dof = large_dof
+        self.max_large = int(max_large)
+        self.n_large = 0
         self.ex = executor
         self.capacity = int(capacity_bytes)
         self.max_members = int(max_members)
@@ -138,16 +154,24 @@ class Server:
         self.used = 0
         self.active = {}  # handle -> Request
 
+    def _large(self, r) -> int:
+        return int(self.large_dof is not None and r.dof >= self.large_dof)
+
     def _next(self, pending, t):
-        """Index of the next request to admit among those arrived by t (or None)."""
-        if not pending or pending[0].arrival > t:
-            return None
-        if self.policy == "fifo":
-            return 0
+        """Index of the next request to admit among those arrived by t (or
+        None): the oldest (fifo, or sjf past max_wait) or the least work (sjf),
+        among the requests the large-request limit lets in now."""
+        full = self.n_large >= self.max_large
         best = None
         for i, r in enumerate(pending):
             if r.arrival > t:
                 break
+            if full and self._large(r):
+                continue
+            if self.policy == "fifo":
+                return i
+            if self.max_wait is not None and t - r.arrival > self.max_wait:
+                return i
             if best is None or r.dof * r.steps < pending[best].dof * pending[best].steps:
                 best = i
         return best
@@ -179,6 +203,7 @@ class Server:
                     continue
                 r.admitted = now()
                 self.used += r.footprint
+                self.n_large += self._large(r)
                 self.active[h] = r
             if not self.active:
                 if pending:
@@ -193,6 +218,7 @@ class Server:
                 if err:
                     r.failed = str(err)
                 self.used -= r.footprint
+                self.n_large -= self._large(r)
                 self.ex.release(h)
                 finished.append(r)
         return metrics(finished + [r for r in requests if r.failed and r not in finished])

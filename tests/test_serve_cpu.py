@@ -220,3 +220,64 @@ def test_arena_fragmentation_defers_admission():
     d = reqs[3]
     assert d.admitted >= reqs[1].done  # waited for B's range
     assert ex.arena.in_use() == 0
+
+
+def test_large_requests_run_one_at_a_time_beside_small_ones():
+    """With a large-request limit no two requests of large_dof DOF or more are
+    resident together, small requests are admitted while a large one runs, and
+    everything completes."""
+    clk = Clock()
+
+    class Watch(FakeExecutor):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.max_large = 0
+            self.small_beside_large = 0
+
+        def admit(self, r):
+            h = super().admit(r)
+            large = [m for m in self.members.values() if m[0].dof >= 5000]
+            self.max_large = max(self.max_large, len(large))
+            if large and r.dof < 5000:
+                self.small_beside_large += 1
+            return h
+
+    reqs = []
+    for i in range(12):
+        dof = 8000 if i % 3 == 0 else 500
+        r = serve.Request(id=i, problem={}, kind="x", prim_args={}, arrival=0.01 * i,
+                          steps=10 if dof > 1000 else 3, dof=dof)
+        reqs.append(r)
+    ex = Watch(clk, rate=1e6)
+    m = serve.Server(ex, 10 ** 15, max_members=4, quantum=1, clock=clk, sleep=clk.sleep,
+                     policy="sjf", large_dof=5000).run(reqs)
+    assert m["completed"] == 12 and m["failed"] == 0
+    assert ex.max_large == 1
+    assert ex.small_beside_large > 0
+    # without the limit the large ones share the device
+    clk2 = Clock()
+    ex2 = Watch(clk2, rate=1e6)
+    for r in reqs:
+        r.admitted = r.done = None
+    serve.Server(ex2, 10 ** 15, max_members=4, quantum=1, clock=clk2, sleep=clk2.sleep,
+                 policy="sjf").run(reqs)
+    assert ex2.max_large > 1
+
+
+def test_sjf_max_wait_admits_the_oldest():
+    """Under sjf a large request waits while smaller ones keep arriving; past
+    max_wait the oldest arrived request goes first."""
+    def run(max_wait):
+        clk = Clock()
+        ex = FakeExecutor(clk, rate=1e6)
+        reqs = [serve.Request(id=0, problem={}, kind="x", prim_args={}, arrival=0.0001,
+                              steps=5, dof=10000)]
+        # small requests (0.0005 s each) arriving every 0.0001 s
+        reqs += [serve.Request(id=i, problem={}, kind="x", prim_args={},
+                               arrival=0.0 if i == 1 else 0.0001 * i, steps=5, dof=100)
+                 for i in range(1, 30)]
+        serve.Server(ex, 10 ** 15, max_members=1, quantum=5, clock=clk, sleep=clk.sleep,
+                     policy="sjf", max_wait=max_wait).run(reqs)
+        return ex.order.index(0)
+    assert run(None) == 29          # passed over until the stream ends
+    assert 0 < run(0.002) < 10
