@@ -418,3 +418,40 @@ def run_sequential(requests: List[Request], capacity_bytes: int, device="cuda:0"
                       policy="fifo").run(requests)
     finally:
         ex.close()
+
+
+def main(argv=None) -> None:
+    """Run the serving mix once on cuda:0 and print its metrics as JSON:
+    `python -m paper_2308_06196_amd.serve --path batched|plain [--rate R]`
+    (rate: Poisson arrivals per second; all requests at t = 0 without it)."""
+    import argparse
+    import json
+
+    from . import workloads as wl
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--path", choices=["batched", "plain"], default="batched")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--rate", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--pool-gb", type=float, default=200.0)
+    ap.add_argument("--members", type=int, default=8)
+    ap.add_argument("--large-dof", type=float, default=2.5e8)
+    a = ap.parse_args(argv)
+    pool = int(a.pool_gb * (1 << 30))
+    reqs = make_requests(wl.serving_requests(n=a.requests, seed=a.seed, rate=a.rate,
+                                             steps=a.steps))
+    if a.path == "batched":
+        ex = BatchExecutor(max_members=a.members, arena_bytes=pool)
+        try:
+            m = Server(ex, pool, max_members=a.members, quantum=4, policy="sjf",
+                       large_dof=a.large_dof or None).run(reqs)
+        finally:
+            ex.close()
+    else:
+        m = run_sequential(reqs, pool, arena=True)
+    print(json.dumps({"path": a.path, "rate": a.rate, **m}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
