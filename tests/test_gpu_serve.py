@@ -67,6 +67,44 @@ def test_batch_members_match_solo_runs_bitwise(torch):
     batch.close()
 
 
+def test_batch_large_member_solo_launches_match_solo_runs_bitwise(torch):
+    """Members of 8192 stage work items or more (filling the device alone) run
+    their RK stages with their solo launches inside the batch (the column
+    sweep where their solver sweeps); beside per-element family members, and
+    finishing at different steps, every state is bitwise its solo run's."""
+    from paper_2308_06196_amd import bgk
+    mix = [
+        (wl.box2d(n=32, order=1, nv1=16, kn=1e-2), "box2d", {"amp": 0.1}, 5),   # 16384 items
+        (wl.box2d(n=24, order=3, nv1=16, kn=3e-3), "box2d", {"amp": 0.05}, 3),  # 9216 items
+        (wl.box2d(n=6, order=3, nv1=8, kn=1e-2), "box2d", {"amp": 0.1}, 6),
+        (wl.sod1d(nelem=40, order=2, nv1=8, kn=1e-2), "sod1d", {"amp": 0.1, "k": 2, "phase": 0.3}, 4),
+    ]
+    _say("batch-large-solo-vs-solo", len(mix))
+    stream = torch.cuda.Stream()
+    solo = []
+    for pb, kind, args, n in mix:
+        s, dt = _solver(torch, pb, kind, args, stream)
+        s.rk3_step(dt, n)
+        solo.append(s.get_state().cpu().numpy())
+        s.close()
+    batch = bgk.Batch(stream, 8)
+    members = []
+    for pb, kind, args, n in mix:
+        s, dt = _solver(torch, pb, kind, args, stream)
+        batch.add(s, dt, n)
+        members.append(s)
+    got = {}
+    for _ in range(20):
+        batch.step(1)
+        for s, err in batch.poll():
+            assert err is None
+            got[members.index(s)] = s.get_state().cpu().numpy()
+    assert len(got) == len(mix) and batch.size() == 0
+    for i in range(len(mix)):
+        assert np.array_equal(got[i], solo[i]), i
+    batch.close()
+
+
 def test_batch_failure_is_isolated(torch):
     from paper_2308_06196_amd import bgk
     _say("batch-failure")
