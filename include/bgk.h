@@ -304,7 +304,10 @@ bgk_status bgk_synchronize(bgk_solver* s);
  * to four sub-steps, each three RK stages of [the equilibrium solves of the
  * members per team size, the diffuse-wall densities, one stage launch per
  * kernel family (dimension, order, storage precision)], each launch covering
- * all members of its kind with one work-group per work unit. The member that
+ * all members of its kind with one work-group per work unit; a member of
+ * 8192 stage work units (element x velocity chunk) or more, which fills the
+ * device alone, runs its stages with the launches bgk_rk3_step makes for it
+ * (column sweeps where its solver sweeps) in place of its family's. The member that
  * moves the most bytes per step takes one step per replay, a member moving W
  * times fewer takes the largest power of two <= min(W, 4) (at most its
  * remaining steps), so small requests are not paced by the largest. Members
