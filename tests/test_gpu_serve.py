@@ -74,23 +74,27 @@ def test_batch_large_member_solo_launches_match_solo_runs_bitwise(torch):
     finishing at different steps, every state is bitwise its solo run's."""
     from paper_2308_06196_amd import bgk
     mix = [
-        (wl.box2d(n=32, order=1, nv1=16, kn=1e-2), "box2d", {"amp": 0.1}, 5),   # 16384 items
-        (wl.box2d(n=24, order=3, nv1=16, kn=3e-3), "box2d", {"amp": 0.05}, 3),  # 9216 items
-        (wl.box2d(n=6, order=3, nv1=8, kn=1e-2), "box2d", {"amp": 0.1}, 6),
-        (wl.sod1d(nelem=40, order=2, nv1=8, kn=1e-2), "sod1d", {"amp": 0.1, "k": 2, "phase": 0.3}, 4),
+        (wl.box2d(n=32, order=1, nv1=16, kn=1e-2), "box2d", {"amp": 0.1}, 5, 0),   # 16384 items
+        (wl.box2d(n=24, order=3, nv1=16, kn=3e-3), "box2d", {"amp": 0.05}, 3, 0),  # 9216 items
+        (wl.box2d(n=32, order=1, nv1=16, kn=1e-2), "box2d", {"amp": 0.1}, 4, 1),   # FP32
+        # diffuse walls: wall densities from the batched launches
+        (wl.channel2d(nx=32, ny=32, order=1, nv1=16, kn=1e-2, uw=0.2, theta_w=1.1), "channel2d",
+         {"amp": 0.05, "k": 1, "phase": 0.0}, 3, 0),
+        (wl.box2d(n=6, order=3, nv1=8, kn=1e-2), "box2d", {"amp": 0.1}, 6, 0),
+        (wl.sod1d(nelem=40, order=2, nv1=8, kn=1e-2), "sod1d", {"amp": 0.1, "k": 2, "phase": 0.3}, 4, 0),
     ]
     _say("batch-large-solo-vs-solo", len(mix))
     stream = torch.cuda.Stream()
     solo = []
-    for pb, kind, args, n in mix:
-        s, dt = _solver(torch, pb, kind, args, stream)
+    for pb, kind, args, n, prec in mix:
+        s, dt = _solver(torch, pb, kind, args, stream, precision=prec)
         s.rk3_step(dt, n)
         solo.append(s.get_state().cpu().numpy())
         s.close()
     batch = bgk.Batch(stream, 8)
     members = []
-    for pb, kind, args, n in mix:
-        s, dt = _solver(torch, pb, kind, args, stream)
+    for pb, kind, args, n, prec in mix:
+        s, dt = _solver(torch, pb, kind, args, stream, precision=prec)
         batch.add(s, dt, n)
         members.append(s)
     got = {}
