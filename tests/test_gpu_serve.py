@@ -76,6 +76,7 @@ def test_batch_large_member_solo_launches_match_solo_runs_bitwise(torch):
     mix = [
         (wl.box2d(n=32, order=1, nv1=16, kn=1e-2), "box2d", {"amp": 0.1}, 5, 0),   # 16384 items
         (wl.box2d(n=24, order=3, nv1=16, kn=3e-3), "box2d", {"amp": 0.05}, 3, 0),  # 9216 items
+        (wl.box2d(n=24, order=2, nv1=16, kn=1e-3), "box2d", {"amp": 0.15}, 2, 0),  # 9216 items
         (wl.box2d(n=32, order=1, nv1=16, kn=1e-2), "box2d", {"amp": 0.1}, 4, 1),   # FP32
         # diffuse walls: wall densities from the batched launches
         (wl.channel2d(nx=32, ny=32, order=1, nv1=16, kn=1e-2, uw=0.2, theta_w=1.1), "channel2d",
